@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the 1D3V PIC/MCC step (push + deposit + MCC + Poisson + moments) on one
+MI355X, in particle-steps/s, next to the FP64 CPU oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--workload production|large|small]
+
+One step is one pass of the whole hot path over every particle of the discharge.
+Prints one JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_PARTICLE_STEP = 36   # read x, vx, vy, vz, id (20 B) + write x, vx, vy, vz (16 B), FP32/u32
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+
+
+def workloads_by_name():
+    import workloads as W
+    return {"production": W.production_helium, "large": W.large_argon, "small": W.small_argon}
+
+
+def kernel_source_sha():
+    p = os.path.join(ROOT, "paper_1608_04601_amd", "csrc", "pic_kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(workload_name):
+    """HBM bytes per launch of the particle pass from the committed rocprofv3 counter summary,
+    or None when the summary is absent or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"pass_kernel_{workload_name}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(disc, steps):
+    """The oracle, unchanged, on the same discharge: load, then `steps` timed steps."""
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    from oracle import Oracle
+    o = Oracle(disc)
+    ps = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ps += len(o.sp[0].x) + len(o.sp[1].x)
+        o.step()
+    dt = time.perf_counter() - t0
+    return dict(value=ps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"{disc.name}: FP64 NumPy oracle, {steps} steps after the load "
+                       f"({disc.n_super[0]}+{disc.n_super[1]} particles), 1 thread, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="production", choices=sorted(workloads_by_name()))
+    ap.add_argument("--cpu-steps", type=int, default=16, help="oracle steps of the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch-blocks", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1608_04601_amd import binding as B
+
+    disc = workloads_by_name()[args.workload]()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    d = B.Discharge(disc, stream=stream.cuda_stream, launch_blocks=args.launch_blocks)
+    try:
+        d.step(args.warmup)
+        d.sync()
+        c0 = d.counters()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        d.step(args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        c1 = d.counters()
+        ps = c1["particle_steps"] - c0["particle_steps"]
+        value = ps / (ms * 1e-3)
+
+        # kernel duration of the particle pass, HIP events around each launch on its stream
+        B.pic_timing(d.h, True)
+        k_steps = min(args.steps, 200)
+        c2 = d.counters()
+        d.step(k_steps)
+        kern_ms, n_launch = B.pic_timing(d.h, False)
+        c3 = d.counters()
+        units = (c3["particle_steps"] - c2["particle_steps"]) / max(k_steps, 1)
+        achieved = BYTES_PER_PARTICLE_STEP * units / (kern_ms * 1e-3) / 1e9
+        traffic = stored_traffic(args.workload)
+    finally:
+        d.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(disc, args.cpu_steps)
+
+    spp = disc.steps_per_period
+    out = {
+        "metric": "particle-steps/s (push+deposit+MCC)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": disc.name,
+            "particles_per_species_initial": int(disc.n_super[0]),
+            "cells": disc.n_cells,
+            "dt_s": disc.dt_s,
+            "steps_per_rf_period": spp,
+            "sort_every": disc.sort_every,
+            "moments_every": disc.moments_every,
+            "alive_particles_mean": ps / args.steps,
+        },
+        "rf_cycles_per_s": (args.steps / (ms * 1e-3)) / spp,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "pass_kernel (fused complete+advance)",
+            "kernel_ms_mean": kern_ms,
+            "launches_timed": n_launch,
+            "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * pic1d.h -- C ABI of an MI355X (gfx950) implementation of the 1D3V electrostatic
+ * PIC/MCC step for capacitively coupled RF discharges (Becker, Kaehlert, Sun, Bonitz,
+ * Loffhagen, "Advanced fluid modelling and PIC/MCC simulations of low-pressure ccrf
+ * discharges", arXiv:1608.04601).
+ *
+ * One step (Sec. 2.5): cloud-in-cell field gather, velocity-Verlet push, full absorption
+ * at both electrodes, cloud-in-cell charge deposition, the Poisson equation (Sec. 2,
+ * Eq. "poisson") with phi(0,t) = V0 sin(2 pi f t) and phi(d,t) = 0 (Sec. 2.2), and
+ * null-collision Monte Carlo collisions for the processes of Table "tab:reactions".
+ *
+ * Conventions for every function:
+ *   - units are SI, energies in eV;
+ *   - every pointer argument is a HOST pointer unless its comment says otherwise;
+ *     output arrays are owned by the caller, input arrays are copied before return;
+ *   - functions return PIC_OK (0) or a negative PIC_E* status and never throw;
+ *   - work is enqueued on one HIP stream (the caller's, or the library's own); device
+ *     faults (capacity, non-finite values) are raised on the device and reported by
+ *     the next synchronising call (pic_sync, pic_moments, pic_get_*); after any error
+ *     the handle is poisoned: every later call returns that first error, and only
+ *     pic_free and pic_last_error remain useful;
+ *   - a handle must not be used from two threads at once.
+ */
+#ifndef PIC1D_H
+#define PIC1D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define PIC_OK          0
+#define PIC_EINVAL     -1  /* invalid argument or configuration (checked on the host)       */
+#define PIC_ENOMEM     -2  /* host or device allocation failed                              */
+#define PIC_EHIP       -3  /* a HIP runtime call failed                                     */
+#define PIC_ECAPACITY  -4  /* particle storage, per-step birth buffer or id space exhausted */
+#define PIC_ENUMERIC   -5  /* a particle coordinate became non-finite                      */
+#define PIC_ESTATE     -6  /* call not allowed in the handle's state                       */
+
+/* ---- collision processes (Table "tab:reactions"; Sec. 2.5 scattering rules) ----
+ * Electron processes see a gas atom at rest; ion processes see an atom drawn from the gas
+ * Maxwellian at T_gas.  ELASTIC/ISOTROPIC scatter isotropically in the centre-of-mass
+ * frame; EXCITATION removes the threshold energy and scatters isotropically; IONIZATION
+ * shares the remaining energy equally between the two electrons (both isotropic) and
+ * creates an ion from the gas Maxwellian at the parent's position; BACKWARD gives the
+ * ion the atom's velocity (charge exchange). */
+#define PIC_E_ELASTIC     0
+#define PIC_E_EXCITATION  1
+#define PIC_E_IONIZATION  2
+#define PIC_I_ISOTROPIC   3
+#define PIC_I_BACKWARD    4
+/* energy frame of a table (Sec. 4.1: He ion data in centre-of-mass energy, Ar in lab) */
+#define PIC_FRAME_LAB 0
+#define PIC_FRAME_CM  1
+#define PIC_MAX_PROCESSES 16
+#define PIC_MAX_CELLS 4096
+
+#define PIC_ELECTRON 0
+#define PIC_ION      1
+
+/* One cross-section table.  sigma(eps) = 0 for eps < threshold_eV; otherwise eps is
+ * raised to emin_eV, then sigma is the last value at or beyond the last point and the
+ * linear interpolation of sigma_m2[k] at eps_k = k * de_eV in between.  LAB tables are
+ * read at 1/2 m_s g^2, CM tables at 1/2 mu g^2 (g: speed relative to the atom). */
+typedef struct pic_xsec {
+    int32_t kind;             /* PIC_E_* or PIC_I_*; the species follows from the kind */
+    int32_t frame;            /* PIC_FRAME_LAB or PIC_FRAME_CM                          */
+    int32_t n_points;         /* >= 2                                                   */
+    int32_t reserved;         /* must be 0                                              */
+    double threshold_eV;      /* >= 0                                                   */
+    double de_eV;             /* > 0                                                    */
+    double emin_eV;           /* >= 0; 0 = no floor (Sec. 4.1 uses 0.1 eV for Ar ions)   */
+    const double* sigma_m2;   /* host, n_points finite values >= 0; copied by pic_init  */
+} pic_xsec;
+
+/* The problem statement (Sec. 2, Table "tab:discharge") and the numerical parameters
+ * (Sec. 4.2, Table "tab:numericalparameters").  The superparticle weight is
+ * W = n_init_m3 * gap_m / n_init_super[0] per m^2, the same for both species; the gas
+ * density is pressure / (k_B T_gas) (Sec. 2.1); the ion mass is the gas mass. */
+typedef struct pic_config {
+    double gap_m;               /* electrode distance d > 0                            */
+    double pressure_Pa;         /* > 0                                                 */
+    double gas_temperature_K;   /* > 0                                                 */
+    double gas_mass_amu;        /* > 0                                                 */
+    double rf_voltage_V;        /* V0 at the powered electrode z = 0 (finite)          */
+    double rf_frequency_Hz;     /* f > 0                                               */
+    double dt_s;                /* time step > 0                                       */
+    double n_init_m3;           /* initial uniform density >= 0                        */
+    double te_init_eV;          /* k_B T of the initial electron Maxwellian, >= 0      */
+    double ti_init_eV;          /* k_B T of the initial ion Maxwellian, >= 0           */
+    int32_t n_cells;            /* 2 .. PIC_MAX_CELLS cells, n_cells + 1 nodes         */
+    int32_t n_xsec;             /* 0 .. PIC_MAX_PROCESSES                              */
+    const pic_xsec* xsec;       /* host array of n_xsec tables, in selection order     */
+    int64_t n_init_super[2];    /* initial particles per species; [0] > 0              */
+    int64_t capacity[2];        /* storage per species, >= n_init_super, < 2^31        */
+    uint64_t seed;              /* Philox key                                          */
+    int32_t sort_every;         /* cell sort + compaction every this many steps; 0 = never */
+    int32_t moments_every;      /* moment sample every this many steps, >= 1           */
+    int32_t max_births_per_step;/* ionisations one step may create, >= 1               */
+    int32_t launch_blocks;      /* workgroups of the particle pass; 0 = automatic      */
+} pic_config;
+
+/* Window averages since the last reset (pic_moments).  Arrays are caller-owned host
+ * arrays of n_nodes = n_cells + 1 doubles, or NULL to skip.  Densities and the ion flux
+ * divide the cloud-in-cell sums by the node volume (dx inside, dx/2 at the electrodes)
+ * and the number of samples; the mean electron energy is the ratio of window sums
+ * (U_e = w_e / n_e, Sec. 2.1), NaN where no electron was sampled. */
+typedef struct pic_moments_out {
+    int32_t n_nodes;            /* in: length of the arrays below                      */
+    int32_t reserved;
+    double* n_e_m3;
+    double* n_i_m3;
+    double* mean_energy_e_eV;
+    double* phi_V;              /* window mean of the node potential                  */
+    double* flux_i_m2s;         /* ion particle flux along z                           */
+    int64_t n_samples;
+    int64_t n_steps;            /* steps in the window                                 */
+    double window_s;
+    double J0_A_m2;             /* mean over whole RF periods of max |J| (Sec. 2.2)    */
+    double flux_i_powered_m2s;  /* ions absorbed at z = 0 per area and time (Table "tab:plasmaparameters") */
+    int64_t absorbed[2][2];     /* [species][electrode 0 = z=0, 1 = z=d] in the window */
+} pic_moments_out;
+
+/* Running counters (pic_get_counters). */
+typedef struct pic_counters {
+    int64_t step;                    /* completed steps n (state at t_n = n dt)        */
+    int64_t n_alive[2];
+    int64_t n_slots[2];              /* storage in use, including absorbed holes       */
+    int64_t next_id[2];
+    int64_t particle_steps;          /* sum over steps of the particles alive at its start */
+    int64_t absorbed_total[2][2];
+    int64_t collisions[PIC_MAX_PROCESSES]; /* real collisions per table, config order   */
+    int64_t numax_violations[2];     /* candidates whose frequency exceeded nu_max      */
+    int64_t births_total;
+    double J_last_A_m2;              /* J^{n-1/2} of the last step (Sec. 2.2)            */
+    double sigma0_C_m2;              /* surface charge eps0 E(0) on the powered electrode */
+    double sigmad_C_m2;              /* surface charge -eps0 E(d) on the grounded one     */
+} pic_counters;
+
+/* Constants the library derived from the configuration (pic_get_derived). */
+typedef struct pic_derived {
+    double dx_m;
+    double n_gas_m3;
+    double weight_m2;
+    double ion_mass_kg;
+    double v_thermal_gas_ms;         /* sqrt(k_B T_gas / M)                             */
+    double numax_s[2];               /* null-collision bound per species                */
+    double p_null[2];                /* 1 - exp(-numax dt)                               */
+    uint32_t threshold[2];           /* candidate iff (philox word >> 8) < threshold    */
+    int32_t steps_per_period;
+    int32_t reserved;
+} pic_derived;
+
+typedef struct pic_handle pic_handle;
+
+/* ---- the production entry points ---- */
+
+/* Validate cfg, derive the constants, allocate device storage, load the uniform
+ * Maxwellian initial state (Sec. 2.2) and solve the field at t = 0.  hip_stream is a
+ * hipStream_t on the current device, or NULL for a stream the library creates.  The
+ * handle keeps the stream; the caller keeps it alive until pic_free.  On error *out is
+ * NULL and the status says why (pic_last_error(NULL) gives the message). */
+int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out);
+
+/* Enqueue n_steps >= 0 PIC/MCC steps (Sec. 2.5) on the handle's stream and return
+ * without waiting.  The collisions of the last step complete lazily at the next step or
+ * at the next call that reads the state. */
+int pic_step(pic_handle* h, int64_t n_steps);
+
+/* Wait for the handle's stream and report deferred device errors. */
+int pic_sync(pic_handle* h);
+
+/* Complete the pending step, synchronise, and write the window averages since the last
+ * reset into *out (arrays sized out->n_nodes == n_cells + 1).  reset != 0 starts a new
+ * window after reading. */
+int pic_moments(pic_handle* h, pic_moments_out* out, int reset);
+
+/* Release the handle and its device storage.  NULL-safe; waits for queued work. */
+void pic_free(pic_handle* h);
+
+/* Message of the last error on h (or of the last failed pic_init when h is NULL).
+ * Valid until the next call on h. */
+const char* pic_last_error(const pic_handle* h);
+
+/* ---- inspection and test hooks ---- */
+
+/* Complete the pending step, synchronise and read the running counters. */
+int pic_get_counters(pic_handle* h, pic_counters* out);
+int pic_get_derived(const pic_handle* h, pic_derived* out);
+
+/* Copy the alive particles of one species (state at t_n, integer-time velocities) into
+ * caller arrays of length capacity; *n_out receives the count.  Positions are metres in
+ * double precision (the device keeps FP32 positions in cell units, whose value in metres
+ * is exact in FP64); velocities are m/s.  If all array pointers are NULL only the count
+ * is returned.  Returns PIC_EINVAL if capacity is too small. */
+int pic_get_particles(pic_handle* h, int species, double* x, float* vx, float* vy, float* vz,
+                      uint32_t* id, int64_t capacity, int64_t* n_out);
+
+/* Replace the particles of one species (n <= capacity, 0 < x < d, finite velocities,
+ * ids < next_id <= 2^32) and the step counter; the field is re-solved at t_step. */
+int pic_set_particles(pic_handle* h, int species, const double* x, const float* vx, const float* vy,
+                      const float* vz, const uint32_t* id, int64_t n, uint32_t next_id, int64_t step);
+
+/* Node charge per area (C/m^2) deposited for the current field, node potential and node
+ * field at t_n; arrays of n_cells + 1 values, NULL to skip. */
+int pic_get_fields(pic_handle* h, double* q_nodes, double* phi, float* e_nodes);
+
+/* Record, for every collision test, the outcome per particle: 0 not a candidate,
+ * 1 null collision, 2 + j table j selected.  Recording costs one byte per particle per
+ * step and is off by default. */
+int pic_set_record_decisions(pic_handle* h, int on);
+
+/* Outcomes of the most recent collision test for the alive particles of one species. */
+int pic_get_decisions(pic_handle* h, int species, uint32_t* id, int8_t* code, int64_t capacity,
+                      int64_t* n_out);
+
+/* Mean duration (ms) of the particle-pass kernel over the last timed window started by
+ * pic_timing(h, 1) and read by pic_timing(h, 0); measured with HIP events on the
+ * handle's stream.  *n_launches receives the number of timed launches. */
+int pic_timing(pic_handle* h, int start, double* mean_ms, int64_t* n_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC1D_H */

@@ -1,0 +1,736 @@
+// Host side of the C ABI declared in include/pic1d.h: configuration checks, derived
+// constants, device storage, launch sequencing, deferred error reporting and the test
+// hooks.  All device work goes through the gfx950 kernels of pic_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "pic1d.h"
+#include "pic_types.hpp"
+
+namespace pic {
+hipError_t launch_pass(int mode, const Params& P, int blocks, int threads, size_t lds, hipStream_t st);
+hipError_t launch_load(const Params& P, int s, int64_t n, double vth, hipStream_t st);
+hipError_t launch_sort(const Params& P, unsigned* cnt, unsigned* cursor, int blocks, int threads, hipStream_t st);
+hipError_t launch_reset_window(const Params& P, hipStream_t st);
+hipError_t set_pass_lds_limit(size_t bytes);
+}  // namespace pic
+
+namespace {
+
+// CODATA 2018
+constexpr double kE0 = 1.602176634e-19;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kKB = 1.380649e-23;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local std::string g_init_error;
+
+int species_of_kind(int kind) { return kind <= PIC_E_IONIZATION ? PIC_ELECTRON : PIC_ION; }
+
+}  // namespace
+
+struct pic_handle {
+    pic_config cfg{};
+    std::vector<pic_xsec> xs;
+    std::vector<std::vector<double>> tables;
+    // derived (Sec. 2.1 gas density, Sec. 2.5 constant weight)
+    double dx = 0, n_gas = 0, W = 0, M = 0, vT = 0;
+    double mass[2] = {0, 0};
+    double numax[2] = {0, 0}, pnull[2] = {0, 0};
+    uint32_t T[2] = {0, 0};
+    int spp = 1;
+    // device
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<void*> allocs;
+    pic::Params P{};
+    unsigned* sort_cnt = nullptr;
+    unsigned* sort_cursor = nullptr;
+    int8_t* dec_store[2] = {nullptr, nullptr};
+    int blocks = 1, threads = 256;
+    size_t lds = 0;
+    int sort_blocks = 1, sort_threads = 256;
+    // sequencing
+    bool pending = false;
+    int since_sort = 0;
+    // errors
+    int status = PIC_OK;
+    std::string err;
+    // timing of the particle pass
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    int64_t n_timed = 0;
+};
+
+namespace {
+
+int fail(pic_handle* h, int code, const std::string& msg) {
+    if (h) {
+        if (h->status == PIC_OK) {
+            h->status = code;
+            h->err = msg;
+        }
+        return h->status;
+    }
+    g_init_error = msg;
+    return code;
+}
+
+bool hip_ok(pic_handle* h, hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    fail(h, PIC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return false;
+}
+
+// sigma_j at frame energy eps (FP64): zero below threshold, floor emin, clamp at the
+// last point, linear interpolation in between.
+double sigma_at(const pic_xsec& p, const std::vector<double>& tab, double eps) {
+    if (eps < p.threshold_eV) return 0.0;
+    const double t = std::max(eps, p.emin_eV) / p.de_eV;
+    const double k = std::floor(t);
+    const int n = p.n_points;
+    if (k >= n - 1) return tab[n - 1];
+    const int kk = (int)k;
+    return tab[kk] + (tab[kk + 1] - tab[kk]) * (t - kk);
+}
+
+// Supremum over the table range of n_gas * sum_j sigma_j * g for species s.  As a function
+// of the lab energy the summed cross section is piecewise linear between the union of
+// all table points, thresholds and floors; on each piece (a + b eps) sqrt(eps) peaks at an
+// end or at eps = -a / (3 b).
+double compute_numax(const pic_handle* h, int s) {
+    std::vector<int> procs;
+    for (size_t j = 0; j < h->xs.size(); ++j)
+        if (species_of_kind(h->xs[j].kind) == s) procs.push_back((int)j);
+    if (procs.empty()) return 0.0;
+    const double m = h->mass[s], M = h->M;
+    std::vector<double> c(h->xs.size(), 1.0);
+    double top = 0.0;
+    for (int j : procs) {
+        c[j] = h->xs[j].frame == PIC_FRAME_LAB ? 1.0 : M / (m + M);
+        top = std::max(top, (h->xs[j].n_points - 1) * h->xs[j].de_eV / c[j]);
+    }
+    std::vector<double> bp = {0.0, top};
+    for (int j : procs) {
+        const pic_xsec& p = h->xs[j];
+        for (int k = 0; k < p.n_points; ++k) bp.push_back(k * p.de_eV / c[j]);
+        bp.push_back(p.threshold_eV / c[j]);
+        bp.push_back(p.emin_eV / c[j]);
+    }
+    std::sort(bp.begin(), bp.end());
+    bp.erase(std::unique(bp.begin(), bp.end()), bp.end());
+    auto total_sigma = [&](double e) {
+        double acc = 0.0;
+        for (int j : procs) acc += sigma_at(h->xs[j], h->tables[j], c[j] * e);
+        return acc;
+    };
+    double best = 0.0;
+    auto consider = [&](double a, double b, double e) {
+        const double sg = std::max(a + b * e, 0.0);
+        best = std::max(best, sg * std::sqrt(2.0 * kE0 * e / m));
+    };
+    for (size_t k = 0; k + 1 < bp.size(); ++k) {
+        const double lo = bp[k], hi = bp[k + 1];
+        if (lo < 0.0 || hi > top || !(hi > lo)) continue;
+        const double m1 = lo + (hi - lo) / 3.0, m2 = lo + 2.0 * (hi - lo) / 3.0;
+        const double s1 = total_sigma(m1), s2 = total_sigma(m2);
+        const double b = (s2 - s1) / (m2 - m1);
+        const double a = s1 - b * m1;
+        consider(a, b, lo);
+        consider(a, b, hi);
+        if (b < 0.0) {
+            const double st = -a / (3.0 * b);
+            if (st > lo && st < hi) consider(a, b, st);
+        }
+    }
+    return h->n_gas * best;
+}
+
+std::string validate(const pic_config* c) {
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    auto nonneg = [](double v) { return std::isfinite(v) && v >= 0.0; };
+    if (!c) return "config is NULL";
+    if (!pos(c->gap_m)) return "gap_m must be > 0";
+    if (!pos(c->pressure_Pa)) return "pressure_Pa must be > 0";
+    if (!pos(c->gas_temperature_K)) return "gas_temperature_K must be > 0";
+    if (!pos(c->gas_mass_amu)) return "gas_mass_amu must be > 0";
+    if (!std::isfinite(c->rf_voltage_V)) return "rf_voltage_V must be finite";
+    if (!pos(c->rf_frequency_Hz)) return "rf_frequency_Hz must be > 0";
+    if (!pos(c->dt_s)) return "dt_s must be > 0";
+    if (!nonneg(c->n_init_m3)) return "n_init_m3 must be >= 0";
+    if (!nonneg(c->te_init_eV) || !nonneg(c->ti_init_eV)) return "initial temperatures must be >= 0";
+    if (c->n_cells < 2 || c->n_cells > PIC_MAX_CELLS) return "n_cells must be in [2, 4096]";
+    if (c->n_xsec < 0 || c->n_xsec > PIC_MAX_PROCESSES) return "n_xsec must be in [0, 16]";
+    if (c->n_xsec > 0 && !c->xsec) return "xsec is NULL";
+    for (int s = 0; s < 2; ++s) {
+        if (c->capacity[s] < 1 || c->capacity[s] >= (int64_t(1) << 31)) return "capacity must be in [1, 2^31)";
+        if (c->n_init_super[s] < 0 || c->n_init_super[s] > c->capacity[s])
+            return "n_init_super must be in [0, capacity]";
+    }
+    if (c->n_init_super[0] < 1) return "n_init_super[0] must be > 0 (it sets the weight)";
+    if (c->sort_every < 0) return "sort_every must be >= 0";
+    if (c->moments_every < 1) return "moments_every must be >= 1";
+    if (c->max_births_per_step < 1) return "max_births_per_step must be >= 1";
+    if (c->launch_blocks < 0 || c->launch_blocks > 65536) return "launch_blocks must be in [0, 65536]";
+    for (int j = 0; j < c->n_xsec; ++j) {
+        const pic_xsec& p = c->xsec[j];
+        if (p.kind < PIC_E_ELASTIC || p.kind > PIC_I_BACKWARD) return "xsec kind out of range";
+        if (p.frame != PIC_FRAME_LAB && p.frame != PIC_FRAME_CM) return "xsec frame out of range";
+        if (p.n_points < 2 || p.n_points > (1 << 22)) return "xsec n_points must be in [2, 2^22]";
+        if (p.reserved != 0) return "xsec reserved must be 0";
+        if (!nonneg(p.threshold_eV) || !pos(p.de_eV) || !nonneg(p.emin_eV)) return "xsec energies invalid";
+        if (!p.sigma_m2) return "xsec sigma_m2 is NULL";
+        for (int k = 0; k < p.n_points; ++k)
+            if (!nonneg(p.sigma_m2[k])) return "xsec sigma_m2 must be finite and >= 0";
+    }
+    return "";
+}
+
+template <typename T>
+bool dev_alloc(pic_handle* h, T** out, size_t count) {
+    *out = nullptr;
+    if (count == 0) return true;
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+        fail(h, PIC_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        return false;
+    }
+    h->allocs.push_back(p);
+    *out = static_cast<T*>(p);
+    return true;
+}
+
+void release(pic_handle* h) {
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void* p : h->allocs) (void)hipFree(p);
+    h->allocs.clear();
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    h->ev.clear();
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    h->stream = nullptr;
+}
+
+int check_device(pic_handle* h) {
+    if (h->status) return h->status;
+    if (!hip_ok(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize")) return h->status;
+    unsigned err = 0;
+    if (!hip_ok(h, hipMemcpy(&err, &h->P.ctrl->err, sizeof(err), hipMemcpyDeviceToHost), "hipMemcpy(err)"))
+        return h->status;
+    if (err & (pic::kErrCapacity | pic::kErrBirths | pic::kErrIds)) {
+        std::string what = (err & pic::kErrCapacity) ? "particle storage exhausted"
+                           : (err & pic::kErrBirths) ? "per-step birth buffer exhausted"
+                                                     : "32-bit particle id space exhausted";
+        return fail(h, PIC_ECAPACITY, what);
+    }
+    if (err & pic::kErrNumeric) return fail(h, PIC_ENUMERIC, "non-finite particle coordinate");
+    return PIC_OK;
+}
+
+int launch_pass_timed(pic_handle* h, int mode) {
+    hipEvent_t a = nullptr, b = nullptr;
+    const bool t = h->timing && (mode & pic::kAdvance);
+    if (t) {
+        const size_t k = (size_t)h->n_timed * 2;
+        if (k + 2 > h->ev.size()) {
+            if (h->ev.size() >= 2 * 8192) {
+                h->timing = false;
+            } else {
+                for (int q = 0; q < 2; ++q) {
+                    hipEvent_t e;
+                    if (!hip_ok(h, hipEventCreate(&e), "hipEventCreate")) return h->status;
+                    h->ev.push_back(e);
+                }
+            }
+        }
+        if (h->timing) {
+            a = h->ev[k];
+            b = h->ev[k + 1];
+            if (!hip_ok(h, hipEventRecord(a, h->stream), "hipEventRecord")) return h->status;
+        }
+    }
+    if (!hip_ok(h, pic::launch_pass(mode, h->P, h->blocks, h->threads, h->lds, h->stream), "pass_kernel launch"))
+        return h->status;
+    if (t && h->timing) {
+        if (!hip_ok(h, hipEventRecord(b, h->stream), "hipEventRecord")) return h->status;
+        h->n_timed += 1;
+    }
+    return PIC_OK;
+}
+
+int complete_pending(pic_handle* h) {
+    if (!h->pending) return PIC_OK;
+    const int rc = launch_pass_timed(h, pic::kComplete);
+    if (rc) return rc;
+    h->pending = false;
+    return PIC_OK;
+}
+
+int read_ctrl(pic_handle* h, pic::Ctrl* c) {
+    if (!hip_ok(h, hipMemcpyAsync(c, h->P.ctrl, sizeof(*c), hipMemcpyDeviceToHost, h->stream), "hipMemcpy(ctrl)"))
+        return h->status;
+    if (!hip_ok(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize")) return h->status;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
+    if (!out) {
+        g_init_error = "out is NULL";
+        return PIC_EINVAL;
+    }
+    *out = nullptr;
+    const std::string bad = validate(cfg);
+    if (!bad.empty()) {
+        g_init_error = bad;
+        return PIC_EINVAL;
+    }
+    pic_handle* h = new (std::nothrow) pic_handle();
+    if (!h) {
+        g_init_error = "out of host memory";
+        return PIC_ENOMEM;
+    }
+    h->cfg = *cfg;
+    for (int j = 0; j < cfg->n_xsec; ++j) {
+        h->xs.push_back(cfg->xsec[j]);
+        h->tables.emplace_back(cfg->xsec[j].sigma_m2, cfg->xsec[j].sigma_m2 + cfg->xsec[j].n_points);
+        h->xs.back().sigma_m2 = nullptr;
+    }
+    h->cfg.xsec = nullptr;
+    const pic_config& c = h->cfg;
+    const int nc = c.n_cells, nn = nc + 1;
+
+    // ---- derived constants
+    h->dx = c.gap_m / nc;
+    h->n_gas = c.pressure_Pa / (kKB * c.gas_temperature_K);
+    h->W = c.n_init_m3 * c.gap_m / (double)c.n_init_super[0];
+    h->M = c.gas_mass_amu * kAmu;
+    h->mass[0] = kMe;
+    h->mass[1] = h->M;
+    h->vT = std::sqrt(kKB * c.gas_temperature_K / h->M);
+    for (int s = 0; s < 2; ++s) {
+        h->numax[s] = compute_numax(h, s);
+        h->pnull[s] = -std::expm1(-h->numax[s] * c.dt_s);
+        h->T[s] = (uint32_t)std::nearbyint(h->pnull[s] * 16777216.0);
+    }
+    h->spp = std::max(1L, std::lround(1.0 / (c.rf_frequency_Hz * c.dt_s)));
+
+    // ---- stream
+    if (!hip_ok(h, hipGetDevice(&h->device), "hipGetDevice")) goto fail_init;
+    if (hip_stream) {
+        h->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (!hip_ok(h, hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking), "hipStreamCreate")) goto fail_init;
+        h->own_stream = true;
+    }
+
+    {
+        pic::Params& P = h->P;
+        const int nbuf = c.sort_every > 0 ? 2 : 1;
+        for (int b = 0; b < nbuf; ++b)
+            for (int s = 0; s < 2; ++s) {
+                const size_t cap = (size_t)c.capacity[s];
+                if (!dev_alloc(h, &P.x[b][s], cap) || !dev_alloc(h, &P.vx[b][s], cap) ||
+                    !dev_alloc(h, &P.vy[b][s], cap) || !dev_alloc(h, &P.vz[b][s], cap) ||
+                    !dev_alloc(h, &P.id[b][s], cap))
+                    goto fail_init;
+            }
+        for (int s = 0; s < 2; ++s) P.cap[s] = c.capacity[s];
+        size_t ntab = 0;
+        for (const pic_xsec& p : h->xs) ntab += (size_t)p.n_points;
+        float* tab = nullptr;
+        if (!dev_alloc(h, &P.ctrl, 1) || !dev_alloc(h, &P.E, nn) || !dev_alloc(h, &P.Q, nn) ||
+            !dev_alloc(h, &P.Q_last, nn) || !dev_alloc(h, &P.phi, nn) || !dev_alloc(h, &P.mom, (size_t)5 * nn) ||
+            !dev_alloc(h, &P.birth_parent, (size_t)c.max_births_per_step) || !dev_alloc(h, &tab, std::max<size_t>(ntab, 1)) ||
+            !dev_alloc(h, &h->sort_cnt, (size_t)2 * nc) || !dev_alloc(h, &h->sort_cursor, (size_t)2 * nc))
+            goto fail_init;
+        P.tab = tab;
+        std::vector<float> htab;
+        htab.reserve(ntab);
+        P.nproc = (int)h->xs.size();
+        for (size_t j = 0; j < h->xs.size(); ++j) {
+            const pic_xsec& p = h->xs[j];
+            pic::ProcDev& d = P.proc[j];
+            const int s = species_of_kind(p.kind);
+            const double m = h->mass[s];
+            const double m_frame = p.frame == PIC_FRAME_LAB ? m : m * h->M / (m + h->M);
+            d.kind = p.kind;
+            d.species = s;
+            d.n = p.n_points;
+            d.off = (int)htab.size();
+            d.thr = (float)p.threshold_eV;
+            d.inv_de = (float)(1.0 / p.de_eV);
+            d.emin = (float)p.emin_eV;
+            d.efac = (float)(0.5 * m_frame / kE0);
+            for (double v : h->tables[j]) htab.push_back((float)(h->n_gas * v));
+        }
+        P.n_cells = nc;
+        P.max_births = c.max_births_per_step;
+        P.moments_every = c.moments_every;
+        P.steps_per_period = h->spp;
+        P.ncf = (float)nc;
+        P.dt_over_dx = (float)(c.dt_s / h->dx);
+        P.dt = (float)c.dt_s;
+        const double q[2] = {-kE0, kE0};
+        for (int s = 0; s < 2; ++s) {
+            P.kick[s] = (float)(0.5 * q[s] / h->mass[s] * c.dt_s);
+            P.half_m_over_e[s] = (float)(0.5 * h->mass[s] / kE0);
+            P.numax[s] = (float)h->numax[s];
+            P.T[s] = h->T[s];
+            P.fa[s] = (float)(h->mass[s] / (h->mass[s] + h->M));
+            P.fb[s] = (float)(h->M / (h->mass[s] + h->M));
+        }
+        P.two_e_over_m_e = (float)(2.0 * kE0 / kMe);
+        P.e_over_m_e = (float)(kE0 / kMe);
+        P.vT = (float)h->vT;
+        P.key0 = (uint32_t)(c.seed & 0xFFFFFFFFu);
+        P.key1 = (uint32_t)(c.seed >> 32);
+        P.dx_d = h->dx;
+        P.eps0 = kEps0;
+        P.e0W = kE0 * h->W;
+        P.V0 = c.rf_voltage_V;
+        P.omega = 2.0 * kPi * c.rf_frequency_Hz;
+        P.dt_d = c.dt_s;
+
+        // launch shape: one workgroup per contiguous particle range; LDS holds the node
+        // field, the private charge grid and the four moment grids
+        h->threads = nn <= 1025 ? 256 : 1024;
+        const size_t pass_lds = 32 * 4 + (size_t)4 * nn * 6;
+        const size_t epi_lds = (size_t)(2 * nn + 18) * 8;
+        const size_t birth_lds = (size_t)pic::kBirthSortCap * 4;
+        h->lds = std::max(pass_lds, std::max(epi_lds, birth_lds));
+        const int64_t total = c.n_init_super[0] + c.n_init_super[1];
+        if (c.launch_blocks > 0) {
+            h->blocks = c.launch_blocks;
+        } else {
+            const int64_t per_block = (int64_t)h->threads * 8;
+            h->blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (total + per_block - 1) / per_block));
+        }
+        h->sort_threads = nc > 1024 ? 1024 : 256;
+        h->sort_blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (total + 8191) / 8192));
+        if (!hip_ok(h, pic::set_pass_lds_limit(h->lds), "hipFuncSetAttribute")) goto fail_init;
+
+        if (!hip_ok(h, hipMemcpyAsync(tab, htab.data(), htab.size() * sizeof(float), hipMemcpyHostToDevice, h->stream),
+                    "upload tables"))
+            goto fail_init;
+        pic::Ctrl c0{};
+        for (int s = 0; s < 2; ++s) {
+            c0.n_slots[s] = c.n_init_super[s];
+            c0.n_alive[s] = c.n_init_super[s];
+            c0.next_id[s] = c.n_init_super[s];
+        }
+        c0.period_valid = 1;
+        if (!hip_ok(h, hipMemcpyAsync(P.ctrl, &c0, sizeof(c0), hipMemcpyHostToDevice, h->stream), "upload ctrl") ||
+            !hip_ok(h, hipMemsetAsync(P.Q, 0, nn * sizeof(double), h->stream), "zero Q") ||
+            !hip_ok(h, hipMemsetAsync(P.mom, 0, 5 * nn * sizeof(double), h->stream), "zero moments") ||
+            !hip_ok(h, hipMemsetAsync(h->sort_cnt, 0, 2 * nc * sizeof(unsigned), h->stream), "zero sort counts"))
+            goto fail_init;
+        const double temps[2] = {c.te_init_eV, c.ti_init_eV};
+        for (int s = 0; s < 2; ++s) {
+            const double vth = std::sqrt(kE0 * temps[s] / h->mass[s]);
+            if (!hip_ok(h, pic::launch_load(P, s, c.n_init_super[s], vth, h->stream), "load_kernel"))
+                goto fail_init;
+        }
+        if (launch_pass_timed(h, pic::kDeposit)) goto fail_init;
+        if (!hip_ok(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize")) goto fail_init;
+    }
+    *out = h;
+    return PIC_OK;
+
+fail_init:
+    g_init_error = h->err;
+    {
+        const int code = h->status ? h->status : PIC_EHIP;
+        release(h);
+        delete h;
+        return code;
+    }
+}
+
+int pic_step(pic_handle* h, int64_t n_steps) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (n_steps < 0) return fail(h, PIC_EINVAL, "n_steps must be >= 0");
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const int mode = pic::kAdvance | (h->pending ? pic::kComplete : 0);
+        if (launch_pass_timed(h, mode)) return h->status;
+        h->pending = true;
+        if (h->cfg.sort_every > 0 && ++h->since_sort >= h->cfg.sort_every) {
+            if (!hip_ok(h, pic::launch_sort(h->P, h->sort_cnt, h->sort_cursor, h->sort_blocks, h->sort_threads, h->stream),
+                        "sort launch"))
+                return h->status;
+            h->since_sort = 0;
+        }
+    }
+    return PIC_OK;
+}
+
+int pic_sync(pic_handle* h) {
+    if (!h) return PIC_EINVAL;
+    return check_device(h);
+}
+
+int pic_moments(pic_handle* h, pic_moments_out* out, int reset) {
+    if (!h || !out) return h ? fail(h, PIC_EINVAL, "out is NULL") : PIC_EINVAL;
+    if (h->status) return h->status;
+    const int nn = h->cfg.n_cells + 1;
+    if (out->n_nodes != nn) return fail(h, PIC_EINVAL, "n_nodes must equal n_cells + 1");
+    if (complete_pending(h)) return h->status;
+    if (check_device(h)) return h->status;
+    pic::Ctrl c;
+    if (read_ctrl(h, &c)) return h->status;
+    std::vector<double> mom((size_t)5 * nn);
+    if (!hip_ok(h, hipMemcpy(mom.data(), h->P.mom, mom.size() * sizeof(double), hipMemcpyDeviceToHost), "read moments"))
+        return h->status;
+    const double N = (double)std::max<int64_t>(c.n_samples, 1);
+    for (int i = 0; i < nn; ++i) {
+        const double V = (i == 0 || i == nn - 1) ? 0.5 * h->dx : h->dx;
+        const double de = mom[i], di = mom[nn + i], en = mom[2 * nn + i], fl = mom[3 * nn + i], ph = mom[4 * nn + i];
+        if (out->n_e_m3) out->n_e_m3[i] = h->W * de / (V * N);
+        if (out->n_i_m3) out->n_i_m3[i] = h->W * di / (V * N);
+        if (out->mean_energy_e_eV) out->mean_energy_e_eV[i] = de > 0.0 ? en / de : NAN;
+        if (out->flux_i_m2s) out->flux_i_m2s[i] = h->W * fl / (V * N);
+        if (out->phi_V) out->phi_V[i] = ph / N;
+    }
+    out->n_samples = c.n_samples;
+    out->n_steps = c.n_steps_window;
+    out->window_s = (double)c.n_steps_window * h->cfg.dt_s;
+    out->J0_A_m2 = c.n_periods > 0 ? c.J_max_sum / (double)c.n_periods : NAN;
+    out->flux_i_powered_m2s = out->window_s > 0 ? h->W * (double)c.absorbed_window[1][0] / out->window_s : NAN;
+    for (int s = 0; s < 2; ++s)
+        for (int e = 0; e < 2; ++e) out->absorbed[s][e] = (int64_t)c.absorbed_window[s][e];
+    if (reset) {
+        if (!hip_ok(h, pic::launch_reset_window(h->P, h->stream), "reset_window")) return h->status;
+        if (check_device(h)) return h->status;
+    }
+    return PIC_OK;
+}
+
+void pic_free(pic_handle* h) {
+    if (!h) return;
+    release(h);
+    delete h;
+}
+
+const char* pic_last_error(const pic_handle* h) {
+    if (!h) return g_init_error.c_str();
+    return h->err.c_str();
+}
+
+int pic_get_counters(pic_handle* h, pic_counters* out) {
+    if (!h || !out) return h ? fail(h, PIC_EINVAL, "out is NULL") : PIC_EINVAL;
+    if (h->status) return h->status;
+    if (complete_pending(h)) return h->status;
+    if (check_device(h)) return h->status;
+    pic::Ctrl c;
+    if (read_ctrl(h, &c)) return h->status;
+    std::memset(out, 0, sizeof(*out));
+    out->step = c.step;
+    for (int s = 0; s < 2; ++s) {
+        out->n_alive[s] = c.n_alive[s];
+        out->n_slots[s] = c.n_slots[s];
+        out->next_id[s] = c.next_id[s];
+        out->numax_violations[s] = (int64_t)c.viol[s];
+        for (int e = 0; e < 2; ++e) out->absorbed_total[s][e] = (int64_t)c.absorbed_total[s][e];
+    }
+    out->particle_steps = c.particle_steps;
+    for (int j = 0; j < PIC_MAX_PROCESSES; ++j) out->collisions[j] = (int64_t)c.coll[j];
+    out->births_total = (int64_t)c.births_total;
+    out->J_last_A_m2 = c.J_last;
+    out->sigma0_C_m2 = c.sigma0;
+    out->sigmad_C_m2 = c.sigmad;
+    return PIC_OK;
+}
+
+int pic_get_derived(const pic_handle* h, pic_derived* out) {
+    if (!h || !out) return PIC_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->dx_m = h->dx;
+    out->n_gas_m3 = h->n_gas;
+    out->weight_m2 = h->W;
+    out->ion_mass_kg = h->M;
+    out->v_thermal_gas_ms = h->vT;
+    for (int s = 0; s < 2; ++s) {
+        out->numax_s[s] = h->numax[s];
+        out->p_null[s] = h->pnull[s];
+        out->threshold[s] = h->T[s];
+    }
+    out->steps_per_period = h->spp;
+    return PIC_OK;
+}
+
+int pic_get_particles(pic_handle* h, int species, double* x, float* vx, float* vy, float* vz, uint32_t* id,
+                      int64_t capacity, int64_t* n_out) {
+    if (!h || !n_out) return h ? fail(h, PIC_EINVAL, "n_out is NULL") : PIC_EINVAL;
+    if (h->status) return h->status;
+    if (species != 0 && species != 1) return fail(h, PIC_EINVAL, "species must be 0 or 1");
+    if (complete_pending(h)) return h->status;
+    if (check_device(h)) return h->status;
+    pic::Ctrl c;
+    if (read_ctrl(h, &c)) return h->status;
+    const int64_t ns = c.n_slots[species];
+    const unsigned b = c.cur;
+    std::vector<float> hx(ns), hvx(ns), hvy(ns), hvz(ns);
+    std::vector<uint32_t> hid(ns);
+    const pic::Params& P = h->P;
+    if (ns > 0 &&
+        (!hip_ok(h, hipMemcpy(hx.data(), P.x[b][species], ns * 4, hipMemcpyDeviceToHost), "copy x") ||
+         !hip_ok(h, hipMemcpy(hvx.data(), P.vx[b][species], ns * 4, hipMemcpyDeviceToHost), "copy vx") ||
+         !hip_ok(h, hipMemcpy(hvy.data(), P.vy[b][species], ns * 4, hipMemcpyDeviceToHost), "copy vy") ||
+         !hip_ok(h, hipMemcpy(hvz.data(), P.vz[b][species], ns * 4, hipMemcpyDeviceToHost), "copy vz") ||
+         !hip_ok(h, hipMemcpy(hid.data(), P.id[b][species], ns * 4, hipMemcpyDeviceToHost), "copy id")))
+        return h->status;
+    int64_t n = 0;
+    for (int64_t i = 0; i < ns; ++i) n += hx[i] > 0.0f;
+    *n_out = n;
+    if (!x && !vx && !vy && !vz && !id) return PIC_OK;
+    if (capacity < n) return fail(h, PIC_EINVAL, "capacity too small for the alive particles");
+    int64_t k = 0;
+    for (int64_t i = 0; i < ns; ++i) {
+        if (!(hx[i] > 0.0f)) continue;
+        if (x) x[k] = (double)hx[i] * h->dx;
+        if (vx) vx[k] = hvx[i];
+        if (vy) vy[k] = hvy[i];
+        if (vz) vz[k] = hvz[i];
+        if (id) id[k] = hid[i];
+        ++k;
+    }
+    return PIC_OK;
+}
+
+int pic_set_particles(pic_handle* h, int species, const double* x, const float* vx, const float* vy, const float* vz,
+                      const uint32_t* id, int64_t n, uint32_t next_id, int64_t step) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (species != 0 && species != 1) return fail(h, PIC_EINVAL, "species must be 0 or 1");
+    if (n < 0 || n > h->cfg.capacity[species]) return fail(h, PIC_EINVAL, "n must be in [0, capacity]");
+    if (step < 0) return fail(h, PIC_EINVAL, "step must be >= 0");
+    if (n > 0 && (!x || !vx || !vy || !vz || !id)) return fail(h, PIC_EINVAL, "particle arrays are NULL");
+    const float ncf = (float)h->cfg.n_cells;
+    std::vector<float> t(n);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(x[i] > 0.0 && x[i] < h->cfg.gap_m)) return fail(h, PIC_EINVAL, "x must be in (0, d)");
+        t[i] = (float)(x[i] / h->dx);
+        if (!(t[i] < ncf)) t[i] = std::nextafter(ncf, 0.0f);
+        if (!(t[i] > 0.0f)) t[i] = std::numeric_limits<float>::denorm_min();
+        if (!std::isfinite(vx[i]) || !std::isfinite(vy[i]) || !std::isfinite(vz[i]))
+            return fail(h, PIC_EINVAL, "velocities must be finite");
+        if (id[i] >= next_id) return fail(h, PIC_EINVAL, "ids must be < next_id");
+    }
+    if (complete_pending(h)) return h->status;
+    if (check_device(h)) return h->status;
+    pic::Ctrl c;
+    if (read_ctrl(h, &c)) return h->status;
+    const unsigned b = c.cur;
+    const pic::Params& P = h->P;
+    if (n > 0 &&
+        (!hip_ok(h, hipMemcpy(P.x[b][species], t.data(), n * 4, hipMemcpyHostToDevice), "copy x") ||
+         !hip_ok(h, hipMemcpy(P.vx[b][species], vx, n * 4, hipMemcpyHostToDevice), "copy vx") ||
+         !hip_ok(h, hipMemcpy(P.vy[b][species], vy, n * 4, hipMemcpyHostToDevice), "copy vy") ||
+         !hip_ok(h, hipMemcpy(P.vz[b][species], vz, n * 4, hipMemcpyHostToDevice), "copy vz") ||
+         !hip_ok(h, hipMemcpy(P.id[b][species], id, n * 4, hipMemcpyHostToDevice), "copy id")))
+        return h->status;
+    c.n_slots[species] = n;
+    c.n_alive[species] = n;
+    c.next_id[species] = next_id == 0 ? 0 : (int64_t)next_id;
+    c.step = step;
+    if (!hip_ok(h, hipMemcpy(h->P.ctrl, &c, sizeof(c), hipMemcpyHostToDevice), "write ctrl")) return h->status;
+    if (!hip_ok(h, hipMemset(h->P.Q, 0, (h->cfg.n_cells + 1) * sizeof(double)), "zero Q")) return h->status;
+    if (launch_pass_timed(h, pic::kDeposit)) return h->status;
+    return check_device(h);
+}
+
+int pic_get_fields(pic_handle* h, double* q_nodes, double* phi, float* e_nodes) {
+    if (!h) return PIC_EINVAL;
+    if (check_device(h)) return h->status;
+    const size_t nn = (size_t)h->cfg.n_cells + 1;
+    if (q_nodes && !hip_ok(h, hipMemcpy(q_nodes, h->P.Q_last, nn * 8, hipMemcpyDeviceToHost), "copy Q")) return h->status;
+    if (phi && !hip_ok(h, hipMemcpy(phi, h->P.phi, nn * 8, hipMemcpyDeviceToHost), "copy phi")) return h->status;
+    if (e_nodes && !hip_ok(h, hipMemcpy(e_nodes, h->P.E, nn * 4, hipMemcpyDeviceToHost), "copy E")) return h->status;
+    return PIC_OK;
+}
+
+int pic_set_record_decisions(pic_handle* h, int on) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (check_device(h)) return h->status;
+    for (int s = 0; s < 2; ++s) {
+        if (on && !h->dec_store[s]) {
+            if (!dev_alloc(h, &h->dec_store[s], (size_t)h->cfg.capacity[s])) return h->status;
+            if (!hip_ok(h, hipMemset(h->dec_store[s], 0, (size_t)h->cfg.capacity[s]), "zero decisions")) return h->status;
+        }
+        h->P.dec[s] = on ? h->dec_store[s] : nullptr;
+    }
+    return PIC_OK;
+}
+
+int pic_get_decisions(pic_handle* h, int species, uint32_t* id, int8_t* code, int64_t capacity, int64_t* n_out) {
+    if (!h || !n_out) return h ? fail(h, PIC_EINVAL, "n_out is NULL") : PIC_EINVAL;
+    if (h->status) return h->status;
+    if (species != 0 && species != 1) return fail(h, PIC_EINVAL, "species must be 0 or 1");
+    if (!h->dec_store[species]) return fail(h, PIC_ESTATE, "decision recording was never enabled");
+    if (check_device(h)) return h->status;
+    pic::Ctrl c;
+    if (read_ctrl(h, &c)) return h->status;
+    const int64_t ns = c.n_slots[species];
+    const unsigned b = c.cur;
+    std::vector<float> hx(ns);
+    std::vector<uint32_t> hid(ns);
+    std::vector<int8_t> hd(ns);
+    if (ns > 0 &&
+        (!hip_ok(h, hipMemcpy(hx.data(), h->P.x[b][species], ns * 4, hipMemcpyDeviceToHost), "copy x") ||
+         !hip_ok(h, hipMemcpy(hid.data(), h->P.id[b][species], ns * 4, hipMemcpyDeviceToHost), "copy id") ||
+         !hip_ok(h, hipMemcpy(hd.data(), h->dec_store[species], ns, hipMemcpyDeviceToHost), "copy decisions")))
+        return h->status;
+    int64_t n = 0;
+    for (int64_t i = 0; i < ns; ++i) n += hx[i] > 0.0f;
+    *n_out = n;
+    if (!id && !code) return PIC_OK;
+    if (capacity < n) return fail(h, PIC_EINVAL, "capacity too small");
+    int64_t k = 0;
+    for (int64_t i = 0; i < ns; ++i) {
+        if (!(hx[i] > 0.0f)) continue;
+        if (id) id[k] = hid[i];
+        if (code) code[k] = hd[i];
+        ++k;
+    }
+    return PIC_OK;
+}
+
+int pic_timing(pic_handle* h, int start, double* mean_ms, int64_t* n_launches) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (start) {
+        if (check_device(h)) return h->status;
+        h->timing = true;
+        h->n_timed = 0;
+        return PIC_OK;
+    }
+    if (check_device(h)) return h->status;
+    double sum = 0.0;
+    for (int64_t k = 0; k < h->n_timed; ++k) {
+        float ms = 0.0f;
+        if (!hip_ok(h, hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]), "hipEventElapsedTime"))
+            return h->status;
+        sum += ms;
+    }
+    if (mean_ms) *mean_ms = h->n_timed ? sum / (double)h->n_timed : 0.0;
+    if (n_launches) *n_launches = h->n_timed;
+    h->timing = false;
+    return PIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,833 @@
+// gfx950 kernels of the 1D3V PIC/MCC step (Becker et al., arXiv:1608.04601, Sec. 2.5).
+//
+// One launch of pass_kernel moves every particle once.  A step of velocity Verlet is
+// split at the field solve: the launch for step n finishes step n-1 (second half kick
+// with E^n, null-collision MCC, ionisation births, moment sample) and starts step n
+// (first half kick with the same E^n, drift, wall absorption, cloud-in-cell deposit).
+// The field E^n is gathered once per particle and used for both half kicks.  The last
+// workgroup to finish (device-scope counter) solves the FP64 Poisson problem for E^{n+1},
+// assigns the ids of the step's ionisation products and does the electrode bookkeeping,
+// so a step is one kernel launch.
+//
+// Particles are FP32 structure-of-arrays streamed once per step with coalesced loads;
+// vy, vz are read only by collision candidates (and electrons on moment steps) and
+// written only after a real collision.  Deposits go to a workgroup-private FP32 copy of
+// the grid in LDS and are flushed to the FP64 grid with one atomic per touched node.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pic_types.hpp"
+
+namespace pic {
+
+// ----------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two 32x32->64
+// products with the published multipliers; the key advances by the published Weyl
+// constants between rounds.  Counter = (particle id, 0, step, (species << 8) | stream).
+// ----------------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+enum Stream : uint32_t { kCollision = 0, kTarget = 1, kScatter = 2, kNewIon = 3, kLoad = 0xFF };
+
+// u = ((w >> 9) + 1/2) 2^-23 in (0, 1); exact in FP32.
+__device__ __forceinline__ float u01(uint32_t w) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
+__device__ __forceinline__ double u01d(uint32_t w) { return ((double)(w >> 9) + 0.5) * 0x1p-23; }
+
+// Box-Muller pair.
+__device__ __forceinline__ void normal2(uint32_t a, uint32_t b, float& z0, float& z1) {
+    const float r = sqrtf(-2.0f * logf(u01(a)));
+    float sn, cs;
+    sincospif(2.0f * u01(b), &sn, &cs);
+    z0 = r * cs;
+    z1 = r * sn;
+}
+
+// Isotropic direction, cos(chi) = 1 - 2 ua, azimuth 2 pi ub; sin(chi) = 2 sqrt(ua (1 - ua)).
+__device__ __forceinline__ void iso_dir(uint32_t a, uint32_t b, float& nx, float& ny, float& nz) {
+    const float ua = u01(a);
+    const float c = 1.0f - 2.0f * ua;
+    const float sn = 2.0f * sqrtf(ua * (1.0f - ua));
+    float sp, cp;
+    sincospif(2.0f * u01(b), &sp, &cp);
+    nx = c;
+    ny = sn * cp;
+    nz = sn * sp;
+}
+
+// n_gas * sigma_j(eps) [1/m]: zero below threshold, floor emin, clamp at the last point,
+// linear interpolation in between.
+__device__ __forceinline__ float nsigma(const ProcDev& p, const float* __restrict__ tab, float eps) {
+    if (eps < p.thr) return 0.0f;
+    const float t = fmaxf(eps, p.emin) * p.inv_de;
+    if (t >= (float)(p.n - 1)) return tab[p.off + p.n - 1];
+    const int k = (int)t;
+    const float f = t - (float)k;
+    const float a = tab[p.off + k];
+    const float b = tab[p.off + k + 1];
+    return fmaf(b - a, f, a);
+}
+
+// Cloud-in-cell cell and weight of a position t > 0 in cell units (both exact).
+__device__ __forceinline__ void cell_of(float t, int nc, int& j, float& w) {
+    j = min((int)t, nc - 1);
+    w = t - (float)j;
+}
+
+__device__ __forceinline__ void lds_add2(float* a, int j, float w, float v) {
+    atomicAdd(&a[j], v - v * w);
+    atomicAdd(&a[j + 1], v * w);
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// LDS counter slots of one workgroup
+enum : int { kCntAbs = 0, kCntColl = 4, kCntViol = 20, kCntErr = 22, kCntLast = 31, kCntSlots = 32 };
+
+struct Lds {
+    uint32_t* cnt;
+    float* E;
+    float* Q;
+    float* M;   // 4 x nn moment sums: dens_e, dens_i, energy_e, flux_i
+};
+
+// After the drift: absorb at the electrodes (Sec. 2.5, ties absorbed) or deposit.
+__device__ __forceinline__ float absorb_or_deposit(const Params& P, const Lds& L, int s, float x) {
+    if (x > 0.0f && x < P.ncf) {
+        int j;
+        float w;
+        cell_of(x, P.n_cells, j, w);
+        lds_add2(L.Q, j, w, s ? 1.0f : -1.0f);
+        return x;
+    }
+    if (x <= 0.0f)
+        atomicAdd(&L.cnt[kCntAbs + 2 * s + 0], 1u);
+    else if (x >= P.ncf)
+        atomicAdd(&L.cnt[kCntAbs + 2 * s + 1], 1u);
+    else
+        atomicOr(&L.cnt[kCntErr], kErrNumeric);
+    return -1.0f;   // hole marker
+}
+
+__device__ __forceinline__ void sample_moments(const Params& P, const Lds& L, int s, float x, float vx,
+                                               float v2) {
+    const int nn = P.n_cells + 1;
+    int j;
+    float w;
+    cell_of(x, P.n_cells, j, w);
+    if (s == 0) {
+        lds_add2(L.M, j, w, 1.0f);
+        lds_add2(L.M + 2 * nn, j, w, P.half_m_over_e[0] * v2);
+    } else {
+        lds_add2(L.M + nn, j, w, 1.0f);
+        lds_add2(L.M + 3 * nn, j, w, vx);
+    }
+}
+
+// One particle of species s in slot i.
+template <int MODE>
+__device__ __forceinline__ void particle(const Params& P, const Lds& L, int s, int64_t i, uint32_t stepf,
+                                         unsigned cur, int64_t ns0, int64_t ns1, bool sample) {
+    float* __restrict__ X = P.x[cur][s];
+    float x = X[i];
+    if (!(x > 0.0f)) {   // hole (or a corrupted coordinate)
+        if (x != x) atomicOr(&L.cnt[kCntErr], kErrNumeric);
+        if ((MODE & kComplete) && P.dec[s]) P.dec[s][i] = 0;
+        return;
+    }
+    if (MODE == kDeposit) {
+        int j;
+        float w;
+        cell_of(x, P.n_cells, j, w);
+        lds_add2(L.Q, j, w, s ? 1.0f : -1.0f);
+        return;
+    }
+    float* __restrict__ VX = P.vx[cur][s];
+    float vx = VX[i];
+    int j;
+    float w;
+    cell_of(x, P.n_cells, j, w);
+    const float E = fmaf(w, L.E[j + 1] - L.E[j], L.E[j]);   // cloud-in-cell gather
+    const float kE = P.kick[s] * E;                          // half kick, Sec. 2.5 Verlet
+    float vy = 0.0f, vz = 0.0f;
+    bool dirty = false;
+
+    if (MODE & kComplete) {
+        vx += kE;   // v^n
+        const uint32_t pid = P.id[cur][s][i];
+        const uint4 A = philox(pid, 0u, stepf, ((uint32_t)s << 8) | kCollision, P.key0, P.key1);
+        int8_t code = 0;
+        bool have_yz = false;
+        if ((A.x >> 8) < P.T[s]) {   // null-collision candidate (integer test)
+            code = 1;
+            vy = P.vy[cur][s][i];
+            vz = P.vz[cur][s][i];
+            have_yz = true;
+            float vtx = 0.0f, vty = 0.0f, vtz = 0.0f;
+            if (s == 1) {   // gas atom from the Maxwellian at T_gas
+                const uint4 B = philox(pid, 0u, stepf, (1u << 8) | kTarget, P.key0, P.key1);
+                float z0, z1, z2, z3;
+                normal2(B.x, B.y, z0, z1);
+                normal2(B.z, B.w, z2, z3);
+                vtx = P.vT * z0;
+                vty = P.vT * z1;
+                vtz = P.vT * z2;
+            }
+            const float gx = vx - vtx, gy = vy - vty, gz = vz - vtz;
+            const float g2 = gx * gx + gy * gy + gz * gz;
+            const float gm = sqrtf(g2);
+            const float R = u01(A.y) * P.numax[s];
+            float c = 0.0f;
+            int sel = -1;
+            for (int q = 0; q < P.nproc; ++q) {
+                const ProcDev& p = P.proc[q];
+                if (p.species != s) continue;
+                c = fmaf(nsigma(p, P.tab, p.efac * g2), gm, c);
+                if (sel < 0 && R < c) sel = q;
+            }
+            if (c > P.numax[s]) atomicAdd(&L.cnt[kCntViol + s], 1u);
+            if (sel >= 0) {
+                code = (int8_t)(2 + sel);
+                atomicAdd(&L.cnt[kCntColl + sel], 1u);
+                const ProcDev& p = P.proc[sel];
+                const uint4 Cw = philox(pid, 0u, stepf, ((uint32_t)s << 8) | kScatter, P.key0, P.key1);
+                float n1x, n1y, n1z;
+                iso_dir(Cw.x, Cw.y, n1x, n1y, n1z);
+                dirty = true;
+                if (p.kind == 0 || p.kind == 3) {   // elastic / isotropic: CM-isotropic two-body
+                    const float fa = P.fa[s], fb = P.fb[s];
+                    const float sgb = fb * gm;
+                    vx = fmaf(sgb, n1x, fmaf(fa, vx, fb * vtx));
+                    vy = fmaf(sgb, n1y, fmaf(fa, vy, fb * vty));
+                    vz = fmaf(sgb, n1z, fmaf(fa, vz, fb * vtz));
+                } else if (p.kind == 1) {   // excitation: lose the threshold energy
+                    const float eps = P.half_m_over_e[0] * g2;
+                    const float sp = sqrtf(fmaxf(eps - p.thr, 0.0f) * P.two_e_over_m_e);
+                    vx = sp * n1x;
+                    vy = sp * n1y;
+                    vz = sp * n1z;
+                } else if (p.kind == 2) {   // ionisation: equal share of eps - eps_iz
+                    const float eps = P.half_m_over_e[0] * g2;
+                    const float sp = sqrtf(fmaxf(eps - p.thr, 0.0f) * P.e_over_m_e);
+                    vx = sp * n1x;
+                    vy = sp * n1y;
+                    vz = sp * n1z;
+                    float n2x, n2y, n2z;
+                    iso_dir(Cw.z, Cw.w, n2x, n2y, n2z);
+                    const uint4 D = philox(pid, 0u, stepf, ((uint32_t)s << 8) | kNewIon, P.key0, P.key1);
+                    float y0, y1, y2, y3;
+                    normal2(D.x, D.y, y0, y1);
+                    normal2(D.z, D.w, y2, y3);
+                    const unsigned k = atomicAdd(&P.ctrl->n_births, 1u);
+                    if ((int)k < P.max_births && ns0 + (int64_t)k < P.cap[0] && ns1 + (int64_t)k < P.cap[1]) {
+                        P.birth_parent[k] = pid;
+                        // children at the parent's position x^n with end-of-step velocities
+                        float cev[3] = {sp * n2x, sp * n2y, sp * n2z};
+                        float civ[3] = {P.vT * y0, P.vT * y1, P.vT * y2};
+                        if (sample) {
+                            sample_moments(P, L, 0, x, cev[0],
+                                           cev[0] * cev[0] + cev[1] * cev[1] + cev[2] * cev[2]);
+                            sample_moments(P, L, 1, x, civ[0], 0.0f);
+                        }
+                        float cex = x, cix = x;
+                        if (MODE & kAdvance) {   // products are moved from the next step on
+                            cev[0] += P.kick[0] * E;
+                            civ[0] += P.kick[1] * E;
+                            cex = absorb_or_deposit(P, L, 0, fmaf(cev[0], P.dt_over_dx, x));
+                            cix = absorb_or_deposit(P, L, 1, fmaf(civ[0], P.dt_over_dx, x));
+                        }
+                        const int64_t se = ns0 + k, si = ns1 + k;
+                        P.x[cur][0][se] = cex;
+                        P.vx[cur][0][se] = cev[0];
+                        P.vy[cur][0][se] = cev[1];
+                        P.vz[cur][0][se] = cev[2];
+                        P.x[cur][1][si] = cix;
+                        P.vx[cur][1][si] = civ[0];
+                        P.vy[cur][1][si] = civ[1];
+                        P.vz[cur][1][si] = civ[2];
+                        if (P.dec[0]) P.dec[0][se] = 0;
+                        if (P.dec[1]) P.dec[1][si] = 0;
+                    }
+                } else {   // backward: the ion leaves with the atom's velocity
+                    vx = vtx;
+                    vy = vty;
+                    vz = vtz;
+                }
+            }
+        }
+        if (P.dec[s]) P.dec[s][i] = code;
+        if (sample) {
+            float v2 = 0.0f;
+            if (s == 0) {
+                if (!have_yz) {
+                    vy = P.vy[cur][s][i];
+                    vz = P.vz[cur][s][i];
+                }
+                v2 = vx * vx + vy * vy + vz * vz;
+            }
+            sample_moments(P, L, s, x, vx, v2);
+        }
+    }
+    if (MODE & kAdvance) {
+        vx += kE;                                  // v^{n+1/2}
+        x = absorb_or_deposit(P, L, s, fmaf(vx, P.dt_over_dx, x));
+        X[i] = x;
+    }
+    VX[i] = vx;
+    if (dirty) {
+        P.vy[cur][s][i] = vy;
+        P.vz[cur][s][i] = vz;
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// Block-wide FP64 scans for the Poisson solve (one workgroup).
+// ----------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_incl_scan(double v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// In-place inclusive scan of a[0..n); scratch holds >= 16 doubles.  Returns the total.
+__device__ double block_incl_scan(double* a, int n, double* scratch) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int per = (n + nt - 1) / nt;
+    const int b = min(tid * per, n), e = min(b + per, n);
+    double s = 0.0;
+    for (int i = b; i < e; ++i) s += a[i];
+    const double ws = wave_incl_scan(s);
+    const int wid = tid >> 6, lane = tid & 63, nw = nt >> 6;
+    if (lane == 63) scratch[wid] = ws;
+    __syncthreads();
+    if (wid == 0) {
+        double t = lane < nw ? scratch[lane] : 0.0;
+        t = wave_incl_scan(t);
+        if (lane < nw) scratch[lane] = t;
+    }
+    __syncthreads();
+    double run = ws - s + (wid ? scratch[wid - 1] : 0.0);
+    for (int i = b; i < e; ++i) {
+        run += a[i];
+        a[i] = run;
+    }
+    const double total = scratch[nw - 1];
+    __syncthreads();
+    return total;
+}
+
+// Poisson with phi_0 = phi0, phi_N = 0 (Sec. 2, 2.2; central differences, Sec. 2.3):
+// D_i = phi_{i+1} - phi_i obeys D_i = D_0 - (dx/eps0) sum_{k=1..i} Q_k, and
+// sum_i D_i = -phi0 fixes D_0; phi follows from a second prefix sum.  Boundary fields by
+// Gauss's law over the half cells next to the electrodes.
+__device__ void solve_field(const Params& P, double* sd, double phi0, double& E0, double& EN) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nc = P.n_cells, nn = nc + 1;
+    double* work = sd;            // nn
+    double* phis = sd + nn;       // nn
+    double* scratch = sd + 2 * nn;   // 16 + 2
+    const double dxe = P.dx_d / P.eps0;
+    for (int i = tid; i < nn; i += nt) {
+        const double q = ld_agent(&P.Q[i]) * P.e0W;
+        P.Q_last[i] = q;
+        P.Q[i] = 0.0;
+        work[i] = (i >= 1 && i < nc) ? q : 0.0;
+        if (i == 0) scratch[16] = q;
+        if (i == nc) scratch[17] = q;
+    }
+    __syncthreads();
+    const double Q0 = scratch[16], QN = scratch[17];
+    const double S = [&] {
+        block_incl_scan(work, nc, scratch);   // work[i] = sum_{k=1..i} Q_k, i < nc
+        // sum_{i<nc} work[i]
+        double s = 0.0;
+        for (int i = tid; i < nc; i += nt) s += work[i];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if ((tid & 63) == 0) scratch[tid >> 6] = s;
+        __syncthreads();
+        double tot = 0.0;
+        for (int w = 0; w < (nt >> 6); ++w) tot += scratch[w];
+        __syncthreads();
+        return tot;
+    }();
+    const double D0 = (dxe * S - phi0) / (double)nc;
+    for (int i = tid; i < nc; i += nt) work[i] = D0 - dxe * work[i];
+    __syncthreads();
+    block_incl_scan(work, nc, scratch);   // work[i] = sum_{k<=i} D_k
+    for (int i = tid; i < nn; i += nt) {
+        double ph = (i == 0) ? phi0 : (i == nc ? 0.0 : phi0 + work[i - 1]);
+        phis[i] = ph;
+        P.phi[i] = ph;
+    }
+    __syncthreads();
+    const double inv2dx = 0.5 / P.dx_d, invdx = 1.0 / P.dx_d;
+    for (int i = tid; i < nn; i += nt) {
+        double e;
+        if (i == 0)
+            e = (phis[0] - phis[1]) * invdx - Q0 / P.eps0;
+        else if (i == nc)
+            e = (phis[nc - 1] - phis[nc]) * invdx + QN / P.eps0;
+        else
+            e = (phis[i - 1] - phis[i + 1]) * inv2dx;
+        P.E[i] = (float)e;
+        if (i == 0) scratch[16] = e;
+        if (i == nc) scratch[17] = e;
+    }
+    __syncthreads();
+    E0 = scratch[16];
+    EN = scratch[17];
+    __syncthreads();
+}
+
+// Ids of this launch's ionisation products: the k-th parent in ascending id order gives
+// next_id_e + k and next_id_i + k.
+__device__ void assign_birth_ids(const Params& P, unsigned char* smem, unsigned cur, int64_t ns0,
+                                 int64_t ns1, unsigned nbv, int64_t nid0, int64_t nid1) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (nbv == 0) return;
+    if (nbv <= (unsigned)kBirthSortCap) {
+        uint32_t* keys = reinterpret_cast<uint32_t*>(smem);
+        unsigned n2 = 1;
+        while (n2 < nbv) n2 <<= 1;
+        for (unsigned k = tid; k < n2; k += nt) keys[k] = k < nbv ? ld_agent(&P.birth_parent[k]) : 0xFFFFFFFFu;
+        __syncthreads();
+        for (unsigned size = 2; size <= n2; size <<= 1) {
+            for (unsigned stride = size >> 1; stride > 0; stride >>= 1) {
+                for (unsigned t = tid; t < n2; t += nt) {
+                    const unsigned partner = t ^ stride;
+                    if (partner > t) {
+                        const bool up = (t & size) == 0;
+                        const uint32_t a = keys[t], b = keys[partner];
+                        if ((a > b) == up) {
+                            keys[t] = b;
+                            keys[partner] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (unsigned k = tid; k < nbv; k += nt) {
+            const uint32_t p = ld_agent(&P.birth_parent[k]);
+            unsigned lo = 0, hi = nbv;
+            while (lo < hi) {
+                const unsigned mid = (lo + hi) >> 1;
+                if (keys[mid] < p) lo = mid + 1; else hi = mid;
+            }
+            P.id[cur][0][ns0 + k] = (uint32_t)(nid0 + lo);
+            P.id[cur][1][ns1 + k] = (uint32_t)(nid1 + lo);
+        }
+        __syncthreads();
+    } else {
+        for (unsigned k = tid; k < nbv; k += nt) {
+            const uint32_t p = ld_agent(&P.birth_parent[k]);
+            unsigned rank = 0;
+            for (unsigned q = 0; q < nbv; ++q) rank += ld_agent(&P.birth_parent[q]) < p;
+            P.id[cur][0][ns0 + k] = (uint32_t)(nid0 + rank);
+            P.id[cur][1][ns1 + k] = (uint32_t)(nid1 + rank);
+        }
+        __syncthreads();
+    }
+}
+
+// Work of the last workgroup of a launch.
+template <int MODE>
+__device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, unsigned cur, int64_t ns0,
+                         int64_t ns1, bool sample) {
+    Ctrl* C = P.ctrl;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nn = P.n_cells + 1;
+    double* sd = reinterpret_cast<double*>(smem);
+    __syncthreads();
+    if (MODE & kComplete) {
+        const unsigned nb = ld_agent(&C->n_births);
+        unsigned nbv = nb;
+        if ((int64_t)nbv > P.max_births) nbv = (unsigned)P.max_births;
+        if ((int64_t)nbv > P.cap[0] - ns0) nbv = (unsigned)(P.cap[0] - ns0);
+        if ((int64_t)nbv > P.cap[1] - ns1) nbv = (unsigned)(P.cap[1] - ns1);
+        const int64_t nid0 = C->next_id[0], nid1 = C->next_id[1];
+        assign_birth_ids(P, smem, cur, ns0, ns1, nbv, nid0, nid1);
+        if (sample)
+            for (int i = tid; i < nn; i += nt) P.mom[4 * nn + i] += P.phi[i];   // phi^n
+        if (tid == 0) {
+            if (nb > nbv) C->err |= (nbv == (unsigned)P.max_births) ? kErrBirths : kErrCapacity;
+            if (nid0 + nbv > 0x100000000ll || nid1 + nbv > 0x100000000ll) C->err |= kErrIds;
+            C->n_slots[0] = ns0 + nbv;
+            C->n_slots[1] = ns1 + nbv;
+            C->next_id[0] = nid0 + nbv;
+            C->next_id[1] = nid1 + nbv;
+            C->n_alive[0] += nbv;
+            C->n_alive[1] += nbv;
+            C->births_total += nbv;
+            C->births_lost += nb - nbv;
+            C->n_births = 0;
+            if (sample) C->n_samples += 1;
+        }
+        __syncthreads();
+    }
+    if (MODE & kAdvance) {
+        double E0, EN;
+        const double t1 = (double)(step + 1) * P.dt_d;
+        solve_field(P, sd, P.V0 * sin(P.omega * t1), E0, EN);
+        if (tid == 0) {
+            unsigned long long a[2][2];
+            for (int s = 0; s < 2; ++s)
+                for (int e = 0; e < 2; ++e) {
+                    a[s][e] = ld_agent(&C->absorbed_step[s][e]);
+                    C->absorbed_step[s][e] = 0;
+                    C->absorbed_total[s][e] += a[s][e];
+                    C->absorbed_window[s][e] += a[s][e];
+                }
+            C->particle_steps += C->n_alive[0] + C->n_alive[1];
+            C->n_alive[0] -= (int64_t)(a[0][0] + a[0][1]);
+            C->n_alive[1] -= (int64_t)(a[1][0] + a[1][1]);
+            const double J = P.eps0 * (E0 - C->E0_prev) / P.dt_d +
+                             P.e0W * ((double)a[0][0] - (double)a[1][0]) / P.dt_d;
+            C->J_last = J;
+            C->E0_prev = E0;
+            C->sigma0 = P.eps0 * E0;
+            C->sigmad = -P.eps0 * EN;
+            const int64_t n1 = step + 1;
+            C->J_period_max = fmax(C->J_period_max, fabs(J));
+            if (n1 % P.steps_per_period == 0) {
+                if (C->period_valid) {
+                    C->J_max_sum += C->J_period_max;
+                    C->n_periods += 1;
+                }
+                C->J_period_max = 0.0;
+                C->period_valid = 1;
+            }
+            C->n_steps_window += 1;
+            C->step = n1;
+        }
+    }
+    if (MODE == kDeposit) {
+        double E0, EN;
+        solve_field(P, sd, P.V0 * sin(P.omega * (double)step * P.dt_d), E0, EN);
+        if (tid == 0) {
+            C->E0_prev = E0;
+            C->sigma0 = P.eps0 * E0;
+            C->sigmad = -P.eps0 * EN;
+        }
+    }
+    if (tid == 0) C->done = 0;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(1024) pass_kernel(Params P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nn = P.n_cells + 1;
+    Ctrl* C = P.ctrl;
+    Lds L;
+    L.cnt = reinterpret_cast<uint32_t*>(smem);
+    L.E = reinterpret_cast<float*>(smem + kCntSlots * 4);
+    L.Q = L.E + nn;
+    L.M = L.Q + nn;
+
+    const int64_t step = C->step;
+    const unsigned cur = C->cur;
+    const int64_t ns0 = C->n_slots[0], ns1 = C->n_slots[1];
+    const bool sample = (MODE & kComplete) && (step % P.moments_every == 0);
+    const uint32_t stepf = (uint32_t)step;
+
+    for (int i = tid; i < kCntSlots; i += nt) L.cnt[i] = 0;
+    for (int i = tid; i < nn; i += nt) {
+        L.E[i] = (MODE == kDeposit) ? 0.0f : P.E[i];
+        L.Q[i] = 0.0f;
+    }
+    if (sample)
+        for (int i = tid; i < 4 * nn; i += nt) L.M[i] = 0.0f;
+    __syncthreads();
+
+    const int64_t total = ns0 + ns1;
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t begin = (int64_t)blockIdx.x * per;
+    const int64_t end = min(begin + per, total);
+    for (int64_t v = begin + tid; v < end; v += nt) {
+        const int s = v >= ns0;
+        particle<MODE>(P, L, s, s ? v - ns0 : v, stepf, cur, ns0, ns1, sample);
+    }
+    __syncthreads();
+
+    for (int i = tid; i < nn; i += nt) {
+        const float q = L.Q[i];
+        if (q != 0.0f) unsafeAtomicAdd(&P.Q[i], (double)q);
+    }
+    if (sample)
+        for (int i = tid; i < 4 * nn; i += nt) {
+            const float m = L.M[i];
+            if (m != 0.0f) unsafeAtomicAdd(&P.mom[i], (double)m);
+        }
+    if (tid < 4) {
+        if (L.cnt[kCntAbs + tid]) atomicAdd(&C->absorbed_step[tid >> 1][tid & 1], (unsigned long long)L.cnt[kCntAbs + tid]);
+    } else if (tid < 4 + kMaxProc) {
+        if (L.cnt[tid]) atomicAdd(&C->coll[tid - kCntColl], (unsigned long long)L.cnt[tid]);
+    } else if (tid < kCntErr) {
+        if (L.cnt[tid]) atomicAdd(&C->viol[tid - kCntViol], (unsigned long long)L.cnt[tid]);
+    } else if (tid == kCntErr) {
+        if (L.cnt[tid]) atomicOr(&C->err, L.cnt[tid]);
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned prev = atomicAdd(&C->done, 1u);
+        L.cnt[kCntLast] = (prev == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!L.cnt[kCntLast]) return;
+    __threadfence();
+    epilogue<MODE>(P, smem, step, cur, ns0, ns1, sample);
+}
+
+// ----------------------------------------------------------------------------------
+// Initial load (Sec. 2.2): uniform positions, Maxwellian velocities, ids 0..n-1.
+// ----------------------------------------------------------------------------------
+__global__ void load_kernel(Params P, int s, int64_t n, double vth) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t tag = ((uint32_t)s << 8) | kLoad;
+    const uint4 A = philox((uint32_t)k, 0u, 0u, tag, P.key0, P.key1);
+    const uint4 B = philox((uint32_t)k, 0u, 1u, tag, P.key0, P.key1);
+    // x = d u in metres, i.e. n_cells u in cell units
+    float x = (float)((double)P.n_cells * u01d(A.x));
+    if (!(x < P.ncf)) x = nextafterf(P.ncf, 0.0f);
+    const double r0 = sqrt(-2.0 * log(u01d(A.y)));
+    double s0, c0, s1, c1;
+    sincospi(2.0 * u01d(A.z), &s0, &c0);
+    const double r1 = sqrt(-2.0 * log(u01d(B.x)));
+    sincospi(2.0 * u01d(B.y), &s1, &c1);
+    P.x[0][s][k] = x;
+    P.vx[0][s][k] = (float)(vth * r0 * c0);
+    P.vy[0][s][k] = (float)(vth * r0 * s0);
+    P.vz[0][s][k] = (float)(vth * r1 * c1);
+    P.id[0][s][k] = (uint32_t)k;
+}
+
+// ----------------------------------------------------------------------------------
+// Periodic cell sort + compaction (performance only; results do not depend on the
+// order because every random number is keyed by particle id).
+// ----------------------------------------------------------------------------------
+__global__ void sort_count_kernel(Params P, unsigned* cnt) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned* h = reinterpret_cast<unsigned*>(smem);
+    const int nc = P.n_cells, tid = threadIdx.x, nt = blockDim.x;
+    const Ctrl* C = P.ctrl;
+    const unsigned cur = C->cur;
+    const int64_t ns0 = C->n_slots[0], ns1 = C->n_slots[1];
+    for (int i = tid; i < 2 * nc; i += nt) h[i] = 0;
+    __syncthreads();
+    const int64_t total = ns0 + ns1;
+    for (int64_t v = (int64_t)blockIdx.x * nt + tid; v < total; v += (int64_t)gridDim.x * nt) {
+        const int s = v >= ns0;
+        const float x = P.x[cur][s][s ? v - ns0 : v];
+        if (x > 0.0f) {
+            int j;
+            float w;
+            cell_of(x, nc, j, w);
+            atomicAdd(&h[s * nc + j], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < 2 * nc; i += nt)
+        if (h[i]) atomicAdd(&cnt[i], h[i]);
+}
+
+__global__ void sort_scan_kernel(Params P, unsigned* cnt, unsigned* cursor) {
+    __shared__ unsigned sh[1024];
+    const int nc = P.n_cells, tid = threadIdx.x, nt = blockDim.x;
+    for (int s = 0; s < 2; ++s) {
+        unsigned* c = cnt + s * nc;
+        unsigned* o = cursor + s * nc;
+        const int per = (nc + nt - 1) / nt;
+        const int b = min(tid * per, nc), e = min(b + per, nc);
+        unsigned sum = 0;
+        for (int i = b; i < e; ++i) sum += c[i];
+        sh[tid] = sum;
+        __syncthreads();
+        for (int off = 1; off < nt; off <<= 1) {
+            const unsigned t = tid >= off ? sh[tid - off] : 0u;
+            __syncthreads();
+            sh[tid] += t;
+            __syncthreads();
+        }
+        unsigned run = sh[tid] - sum;
+        for (int i = b; i < e; ++i) {
+            o[i] = run;
+            run += c[i];
+            c[i] = 0;
+        }
+        if (tid == nt - 1) P.ctrl->sort_alive[s] = sh[nt - 1];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(1024) sort_scatter_kernel(Params P, unsigned* cursor) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nc = P.n_cells, tid = threadIdx.x, nt = blockDim.x;
+    unsigned* h = reinterpret_cast<unsigned*>(smem);   // 2 nc local counts, then cursors
+    unsigned* base = h + 2 * nc;                        // 2 nc reserved bases
+    unsigned* flag = base + 2 * nc;
+    Ctrl* C = P.ctrl;
+    const unsigned cur = C->cur, nxt = cur ^ 1u;
+    const int64_t ns0 = C->n_slots[0], ns1 = C->n_slots[1];
+    for (int i = tid; i < 2 * nc; i += nt) h[i] = 0;
+    __syncthreads();
+    const int64_t total = ns0 + ns1;
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t begin = (int64_t)blockIdx.x * per;
+    const int64_t end = min(begin + per, total);
+    for (int64_t v = begin + tid; v < end; v += nt) {
+        const int s = v >= ns0;
+        const float x = P.x[cur][s][s ? v - ns0 : v];
+        if (x > 0.0f) {
+            int j;
+            float w;
+            cell_of(x, nc, j, w);
+            atomicAdd(&h[s * nc + j], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < 2 * nc; i += nt) {
+        const unsigned c = h[i];
+        base[i] = c ? atomicAdd(&cursor[i], c) : 0u;
+        h[i] = 0;
+    }
+    __syncthreads();
+    for (int64_t v = begin + tid; v < end; v += nt) {
+        const int s = v >= ns0;
+        const int64_t i = s ? v - ns0 : v;
+        const float x = P.x[cur][s][i];
+        if (x > 0.0f) {
+            int j;
+            float w;
+            cell_of(x, nc, j, w);
+            const unsigned pos = base[s * nc + j] + atomicAdd(&h[s * nc + j], 1u);
+            P.x[nxt][s][pos] = x;
+            P.vx[nxt][s][pos] = P.vx[cur][s][i];
+            P.vy[nxt][s][pos] = P.vy[cur][s][i];
+            P.vz[nxt][s][pos] = P.vz[cur][s][i];
+            P.id[nxt][s][pos] = P.id[cur][s][i];
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned prev = atomicAdd(&C->done, 1u);
+        flag[0] = (prev == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!flag[0] || tid != 0) return;
+    __threadfence();
+    C->n_slots[0] = (int64_t)ld_agent(&C->sort_alive[0]);
+    C->n_slots[1] = (int64_t)ld_agent(&C->sort_alive[1]);
+    C->cur = nxt;
+    C->done = 0;
+}
+
+// Moment window reset (kernel rather than a memset so it can sit in a captured graph).
+__global__ void reset_window_kernel(Params P) {
+    const int nn = P.n_cells + 1;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 5 * nn; i += gridDim.x * blockDim.x) P.mom[i] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Ctrl* C = P.ctrl;
+        C->n_samples = 0;
+        C->n_steps_window = 0;
+        C->n_periods = 0;
+        C->J_period_max = 0.0;
+        C->J_max_sum = 0.0;
+        C->period_valid = (C->step % P.steps_per_period) == 0;
+        for (int s = 0; s < 2; ++s)
+            for (int e = 0; e < 2; ++e) C->absorbed_window[s][e] = 0;
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// Launchers (called by the host library).
+// ----------------------------------------------------------------------------------
+hipError_t launch_pass(int mode, const Params& P, int blocks, int threads, size_t lds, hipStream_t st) {
+    switch (mode) {
+        case kComplete | kAdvance:
+            hipLaunchKernelGGL(pass_kernel<kComplete | kAdvance>, dim3(blocks), dim3(threads), lds, st, P);
+            break;
+        case kAdvance:
+            hipLaunchKernelGGL(pass_kernel<kAdvance>, dim3(blocks), dim3(threads), lds, st, P);
+            break;
+        case kComplete:
+            hipLaunchKernelGGL(pass_kernel<kComplete>, dim3(blocks), dim3(threads), lds, st, P);
+            break;
+        case kDeposit:
+            hipLaunchKernelGGL(pass_kernel<kDeposit>, dim3(blocks), dim3(threads), lds, st, P);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_load(const Params& P, int s, int64_t n, double vth, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int threads = 256;
+    const int64_t blocks = (n + threads - 1) / threads;
+    hipLaunchKernelGGL(load_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, P, s, n, vth);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(const Params& P, unsigned* cnt, unsigned* cursor, int blocks, int threads, hipStream_t st) {
+    const size_t lds_count = (size_t)2 * P.n_cells * sizeof(unsigned);
+    hipLaunchKernelGGL(sort_count_kernel, dim3(blocks), dim3(threads), lds_count, st, P, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(1024), 0, st, P, cnt, cursor);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds_scatter = (size_t)4 * P.n_cells * sizeof(unsigned) + 16;
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(blocks), dim3(threads), lds_scatter, st, P, cursor);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_window(const Params& P, hipStream_t st) {
+    hipLaunchKernelGGL(reset_window_kernel, dim3(8), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+
+hipError_t set_pass_lds_limit(size_t bytes) {
+    const int b = (int)bytes;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete | kAdvance>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kAdvance>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kDeposit>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    return e;
+}
+
+}  // namespace pic

@@ -1,0 +1,112 @@
+// Data layout shared by the host library (pic_api.cpp) and the gfx950 kernels
+// (pic_kernels.hip).  Particle state is FP32 structure-of-arrays in HBM; the grid
+// quantities that feed the Poisson solve and the electrode bookkeeping are FP64.
+// Positions are stored in cell units t = x/dx in [0, n_cells]: the cloud-in-cell cell
+// and weight are then exact (j = floor(t), w = t - j) and the far electrode is exactly
+// t = n_cells; the resolution in metres equals that of an FP32 position in metres.
+#pragma once
+#include <cstdint>
+
+namespace pic {
+
+constexpr int kMaxProc = 16;
+constexpr int kMaxCells = 4096;
+constexpr int kBirthSortCap = 2048;   // births per step ranked in LDS; more take a slow path
+
+// particle-pass modes (bit set)
+constexpr int kComplete = 1;   // finish the previous step: second half kick, MCC, births, moments
+constexpr int kAdvance = 2;    // start the next step: first half kick, drift, absorb, deposit, solve
+constexpr int kDeposit = 4;    // deposit only and solve at the current time (load / set_particles)
+
+// device error bits
+constexpr uint32_t kErrCapacity = 1u;   // particle storage exhausted by births
+constexpr uint32_t kErrNumeric = 2u;    // non-finite coordinate
+constexpr uint32_t kErrBirths = 4u;     // per-step birth buffer exhausted
+constexpr uint32_t kErrIds = 8u;        // 32-bit id space exhausted
+
+// Control block: one per discharge, device resident, read by every kernel at launch and
+// updated by the last workgroup of each launch (so it stays valid under graph replay).
+struct Ctrl {
+    int64_t step;                 // state time index n
+    int64_t n_slots[2];           // storage in use (alive + absorbed holes)
+    int64_t n_alive[2];
+    int64_t next_id[2];
+    int64_t particle_steps;
+    unsigned long long absorbed_step[2][2];
+    unsigned long long absorbed_total[2][2];
+    unsigned long long absorbed_window[2][2];
+    unsigned long long coll[kMaxProc];
+    unsigned long long viol[2];
+    unsigned long long births_total;
+    unsigned long long births_lost;
+    unsigned int n_births;        // births of the running launch
+    unsigned int done;            // workgroups finished in the running launch
+    unsigned int err;
+    unsigned int cur;             // live particle buffer set (0/1); the sort flips it
+    double E0_prev;
+    double J_last;
+    double sigma0, sigmad;
+    int64_t n_samples;
+    int64_t n_steps_window;
+    int64_t n_periods;
+    double J_period_max;
+    double J_max_sum;
+    int32_t period_valid;
+    int32_t pad;
+    unsigned long long sort_alive[2];  // alive count found by the sort histogram
+};
+
+struct ProcDev {
+    int32_t kind;
+    int32_t species;
+    int32_t n;          // table points
+    int32_t off;        // offset into the table array
+    float thr;          // threshold [eV]
+    float inv_de;       // 1/de [1/eV]
+    float emin;         // energy floor [eV]
+    float efac;         // frame energy per g^2 [eV s^2/m^2]
+};
+
+struct Params {
+    // particle storage [buffer set][species]
+    float* x[2][2];      // position in cell units; <= 0 marks an absorbed slot
+    float* vx[2][2];
+    float* vy[2][2];
+    float* vz[2][2];
+    uint32_t* id[2][2];
+    int64_t cap[2];
+    Ctrl* ctrl;
+    float* E;            // node field, FP32 copy for the gather [nn]
+    double* Q;           // node charge accumulator, units of W e0 [nn]
+    double* Q_last;      // charge of the last solve [C/m^2] [nn]
+    double* phi;         // node potential [V] [nn]
+    double* mom;         // moment window sums [5][nn]: dens_e, dens_i, energy_e, flux_i, phi
+    uint32_t* birth_parent;   // [max_births]
+    int8_t* dec[2];      // decision record per slot, or null
+    const float* tab;    // n_gas * sigma tables [1/m]
+    ProcDev proc[kMaxProc];
+    int32_t nproc;
+    int32_t n_cells;
+    int32_t max_births;
+    int32_t moments_every;
+    int32_t steps_per_period;
+    int32_t pad0;
+    float ncf;           // n_cells as float: the grounded electrode in cell units
+    float dt_over_dx;    // drift factor for positions in cell units
+    float dt;
+    float kick[2];       // 1/2 (q/m) dt
+    float half_m_over_e[2];   // 1/2 m / e0 (lab energy per g^2)
+    float two_e_over_m_e;     // 2 e0 / m_e
+    float e_over_m_e;         // e0 / m_e
+    float vT;                 // sqrt(k_B T_gas / M)
+    float numax[2];
+    uint32_t T[2];
+    float fa[2], fb[2];       // m/(m+M), M/(m+M)
+    uint32_t key0, key1;
+    double dx_d;
+    double eps0;
+    double e0W;               // e0 * W: node charge per unit of deposited weight
+    double V0, omega, dt_d;
+};
+
+}  // namespace pic

@@ -1,0 +1,104 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every function that
+include/pic1d.h declares, the ctypes layouts match the C layouts, and invalid
+configurations are rejected on the host with PIC_EINVAL before any device work."""
+import ctypes as C
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_1608_04601_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pic1d.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = B.load_library()
+    names = declared_functions()
+    assert set(names) == set(B.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r" T (pic_[a-z_]+)$", out, flags=re.M))
+    for n in names:
+        assert n in exported, n
+        assert getattr(lib, n) is not None
+
+
+STRUCTS = {
+    "pic_xsec": B.pic_xsec, "pic_config": B.pic_config, "pic_moments_out": B.pic_moments_out,
+    "pic_counters": B.pic_counters, "pic_derived": B.pic_derived,
+}
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_struct_layouts_match_header(tmp_path):
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic1d.h"', 'int main(void) {']
+    for name, cls in STRUCTS.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for name, cls in STRUCTS.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
+
+
+def _bad(**kw):
+    return W.small_argon(n_super=1000).replace(**kw)
+
+
+@pytest.mark.parametrize("disc, msg", [
+    (_bad(gap_m=0.0), "gap_m"),
+    (_bad(pressure_Pa=-1.0), "pressure"),
+    (_bad(dt_s=float("nan")), "dt_s"),
+    (_bad(n_cells=1), "n_cells"),
+    (_bad(n_cells=4097), "n_cells"),
+    (_bad(capacity=(10, 10)), "n_init_super"),
+    (_bad(n_super=(0, 10)), "n_init_super"),
+    (_bad(moments_every=0), "moments_every"),
+    (_bad(sort_every=-1), "sort_every"),
+    (_bad(max_births_per_step=0), "max_births"),
+    (_bad(processes=tuple([W.argon_like()[0]] * 17)), "n_xsec"),
+    (_bad(processes=(W.Process(W.E_ELASTIC, 0, 0.0, 0.1, 0.0, np.array([1e-19])),)), "n_points"),
+    (_bad(processes=(W.Process(W.E_ELASTIC, 0, 0.0, 0.1, 0.0, np.array([1e-19, -1.0])),)), "sigma"),
+    (_bad(processes=(W.Process(W.E_ELASTIC, 0, 0.0, 0.0, 0.0, np.array([1e-19, 1e-19])),)), "energies"),
+    (_bad(processes=(W.Process(7, 0, 0.0, 0.1, 0.0, np.array([1e-19, 1e-19])),)), "kind"),
+    (_bad(processes=(W.Process(0, 2, 0.0, 0.1, 0.0, np.array([1e-19, 1e-19])),)), "frame"),
+])
+def test_invalid_config_rejected_on_host(disc, msg):
+    with pytest.raises(B.PicError) as e:
+        B.pic_init(B.Config(disc))
+    assert e.value.status == B.PIC_EINVAL
+    assert msg in str(e.value)
+    assert msg in B.pic_last_error(None)
+
+
+def test_null_arguments():
+    lib = B.load_library()
+    lib.pic_free(None)  # NULL-safe
+    assert lib.pic_step(None, 1) == B.PIC_EINVAL
+    assert lib.pic_sync(None) == B.PIC_EINVAL
+    assert lib.pic_init(None, None, None) == B.PIC_EINVAL
+    h = C.c_void_p()
+    assert lib.pic_init(None, None, C.byref(h)) == B.PIC_EINVAL and not h

@@ -1,0 +1,237 @@
+"""GPU path against the FP64 oracle, through the C ABI (libpic1d.so).
+
+Single-step protocol: read the GPU's FP32 state at step k (exact in FP64), give it to the
+oracle, advance both by one step with the same ids and counters, and compare per id:
+positions within 1e-5 d, velocities within 1e-5 max(|v|, v_th), node fields within 1e-5 of
+their maxima, identical collision-candidate sets (integer test), identical process
+choices except where the oracle's decision margin |R - c_j| < 1e-5 nu_max, identical
+ionisation-product ids, and the one-sample moments of the end-of-step state.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import MARGIN, REL_FIELD, REL_V, REL_X, log, oracle_input, vth
+from oracle import Oracle, derive
+from paper_1608_04601_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+def _helium_small(n=20_011, seed=5):
+    top = 400.0
+    procs = W.helium_like(top, top) + (
+        W.Process(W.I_ISOTROPIC, W.FRAME_CM, 0.0, 0.1, 0.0, W.constant_table(2e-19, top, 0.1)),)
+    return W.production_helium(seed=seed, n_super=n).replace(
+        processes=procs, capacity=(4 * n, 4 * n), n_cells=96, dt_s=1.0 / (13.56e6 * 400))
+
+
+CASES = {
+    "argon_128c_20k": lambda: W.small_argon(seed=0),
+    "argon_ragged_12347": lambda: W.small_argon(seed=3, n_super=12_347).replace(n_cells=77),
+    "helium_cm_isotropic": _helium_small,
+}
+
+
+def test_derived_constants_match_oracle():
+    for name, mk in list(CASES.items()) + [("production_helium", W.production_helium),
+                                            ("large_argon", lambda: W.large_argon(n_super=1000))]:
+        disc = mk()
+        cfg = disc.replace(n_super=(min(disc.n_super[0], 1000), min(disc.n_super[1], 1000)),
+                           capacity=(1000, 1000))
+        cfg = cfg.replace(n_init_m3=disc.n_init_m3 * cfg.n_super[0] / disc.n_super[0])
+        log(f"derived: {name}")
+        with B.Discharge(cfg) as d:
+            g = d.derived()
+        o = derive(cfg)
+        assert np.isclose(g["dx"], o.dx, rtol=1e-15)
+        assert np.isclose(g["n_gas"], o.n_gas, rtol=1e-15)
+        assert np.isclose(g["W"], o.W, rtol=1e-15)
+        assert g["steps_per_period"] == o.steps_per_period
+        for s in (0, 1):
+            assert np.isclose(g["numax"][s], o.numax[s], rtol=1e-12), (name, s)
+            assert g["T"][s] == o.T[s], (name, s)
+
+
+def test_initial_load_matches_oracle():
+    cfg = W.small_argon(seed=7)
+    log("initial load")
+    with B.Discharge(cfg) as d:
+        c = d.counters()
+        assert c["n_alive"] == cfg.n_super and c["step"] == 0
+        o = Oracle(cfg)
+        for s in (0, 1):
+            p = d.particles(s)
+            k = np.argsort(p["id"])
+            S = o.sp[s]
+            assert np.array_equal(p["id"][k], S.id.astype(np.uint32))
+            # the device rounds the FP64 load to FP32 (positions in cell units)
+            assert np.max(np.abs(p["x"][k] - S.x)) <= 1e-7 * cfg.gap_m
+            for comp, key in enumerate(("vx", "vy", "vz")):
+                ref = S.v[:, comp]
+                assert np.max(np.abs(p[key][k] - ref)) <= 1e-6 * np.abs(ref).max()
+        f = d.fields()
+        o.set_state(0, oracle_input(d, c))
+        assert np.max(np.abs(f["E"] - o.E)) <= REL_FIELD * np.abs(o.E).max()
+        assert np.max(np.abs(f["phi"] - o.phi)) <= REL_FIELD * max(np.abs(o.phi).max(), cfg.rf_voltage_V)
+        assert np.allclose(f["Q"], o.Q, rtol=0, atol=1e-6 * np.abs(o.Q).max())
+
+
+def _compare_decisions(o, s, decisions, next_id_before):
+    """Candidates identical; process choices identical outside the margin band.  Returns the
+    GPU's choice per candidate id and the ids whose choice legitimately differs."""
+    rec = o.last[f"mcc{s}"]
+    did, dcode = decisions
+    old = did.astype(np.int64) < next_id_before
+    did, dcode = did[old].astype(np.int64), dcode[old]
+    cand_gpu = np.sort(did[dcode >= 1])
+    order = np.argsort(rec["candidates"].astype(np.int64), kind="stable")
+    cand_orc = rec["candidates"].astype(np.int64)[order]
+    assert np.array_equal(cand_gpu, cand_orc), (s, len(cand_gpu), len(cand_orc))
+    gmap = dict(zip(did.tolist(), dcode.tolist()))
+    g_sel = np.array([gmap[i] - 2 if gmap[i] >= 2 else -1 for i in cand_orc.tolist()], dtype=np.int64)
+    o_sel = rec["selected"][order]
+    differ = g_sel != o_sel
+    excused = rec["margin"][order] < MARGIN * o.d.numax[s]
+    assert np.all(excused[differ]), (s, int(differ.sum()), int((differ & ~excused).sum()))
+    return dict(zip(cand_orc.tolist(), g_sel.tolist())), set(cand_orc[differ].tolist())
+
+
+def _compare_species(o, s, g_after, unsure, skip_ids_from, disc):
+    """Per-id state after one step; ids in `unsure` and ids >= skip_ids_from are skipped."""
+    S = o.state(s)
+    gid = g_after["id"].astype(np.int64)
+    oid = S["id"].astype(np.int64)
+    gid_c = gid[gid < skip_ids_from]
+    oid_c = oid[oid < skip_ids_from]
+    # the same particles survive (absorption ties at FP32 resolution excepted)
+    only_g = np.setdiff1d(gid_c, oid_c)
+    only_o = np.setdiff1d(oid_c, gid_c)
+    assert len(only_g) + len(only_o) <= 2, (s, only_g[:5], only_o[:5])
+    common, ig, io = np.intersect1d(gid, oid, return_indices=True)
+    keep = np.array([(i not in unsure) and i < skip_ids_from for i in common.tolist()], dtype=bool)
+    ig, io = ig[keep], io[keep]
+    dx = np.abs(g_after["x"][ig] - S["x"][io])
+    assert dx.max(initial=0) <= REL_X * disc.gap_m, (s, dx.max())
+    vt = vth(o, s)
+    for key in ("vx", "vy", "vz"):
+        ref = S[key][io]
+        dv = np.abs(g_after[key][ig] - ref)
+        lim = REL_V * np.maximum(np.abs(ref), vt)
+        bad = dv > lim
+        assert not bad.any(), (s, key, int(bad.sum()), float((dv / lim).max()))
+    return len(ig)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_single_step_parity(case):
+    disc = CASES[case]()
+    nn = disc.n_cells + 1
+    checkpoints = [0, 1, 9, 60, 250]
+    log(f"single-step parity: {case} N={disc.n_super} cells={disc.n_cells}")
+    with B.Discharge(disc) as d:
+        B.pic_set_record_decisions(d.h, True)
+        done = 0
+        total_births = 0
+        for k in checkpoints:
+            d.step(k - done)
+            done = k
+            c0 = d.counters()
+            if c0["n_alive"][0] == 0:
+                break
+            o = Oracle(disc, load=False)
+            o.set_state(k, oracle_input(d, c0))
+            B.pic_moments(d.h, nn, reset=True)
+            o.reset_moments()
+            d.step(1)
+            done += 1
+            o.step()
+            g = [None, None]
+            for s in (0, 1):
+                p = d.particles(s)
+                g[s] = p
+            c1 = d.counters()
+            f = d.fields()
+            log(f"  step {k}->{k + 1}: alive gpu {c1['n_alive']} oracle {(len(o.sp[0].x), len(o.sp[1].x))}")
+            # fields at t_{k+1}
+            assert np.max(np.abs(f["E"] - o.E)) <= REL_FIELD * np.abs(o.E).max()
+            assert np.max(np.abs(f["phi"] - o.phi)) <= REL_FIELD * max(np.abs(o.phi).max(), disc.rf_voltage_V)
+            assert np.isclose(c1["J_last"], o.J, rtol=1e-4, atol=1e-6 * abs(o.J) + 1e-9)
+            # decisions, then births: the ionising parents agree except for excused choices
+            choice, unsure = {}, [set(), set()]
+            for s in (0, 1):
+                ch, unsure[s] = _compare_decisions(o, s, B.pic_get_decisions(d.h, s), c0["next_id"][s])
+                choice.update({(s, i): j for i, j in ch.items()})
+            iz = [j for j, p in enumerate(disc.processes) if p.kind == W.E_IONIZATION]
+            g_par = {i for (s, i), j in choice.items() if s == 0 and j in iz}
+            o_par = set(o.last["births"]["parent"].astype(np.int64).tolist())
+            assert (g_par ^ o_par) <= unsure[0]
+            nb_g = c1["next_id"][0] - c0["next_id"][0]
+            assert nb_g == len(g_par) and c1["next_id"][1] - c0["next_id"][1] == nb_g
+            same_births = g_par == o_par
+            if same_births:
+                assert c1["next_id"] == (o.sp[0].next_id, o.sp[1].next_id)
+            total_births += nb_g
+            for s in (0, 1):
+                # products keep comparable ids only when the parent sets agree
+                skip = 1 << 62 if same_births else c0["next_id"][s]
+                n_cmp = _compare_species(o, s, g[s], unsure[s], skip, disc)
+                assert n_cmp > 0.99 * len(o.sp[s].x) - len(unsure[s]) - 4
+            # absorption counts per electrode
+            ab = c1["absorbed_total"] - c0["absorbed_total"]
+            assert np.abs(ab - o.last["absorbed"]).sum() <= 2
+            # one-sample moments of the end-of-step state
+            mg = B.pic_moments(d.h, nn)
+            mo = o.moments()
+            assert mg["n_samples"] == mo["n_samples"] == 1
+            for key in ("n_e", "n_i", "flux_i", "phi"):
+                scale = np.abs(mo[key]).max() + 1e-30
+                assert np.max(np.abs(mg[key] - mo[key])) <= 2e-4 * scale, key
+            both = np.isfinite(mo["mean_energy_e"]) & np.isfinite(mg["mean_energy_e"])
+            assert np.array_equal(np.isfinite(mo["mean_energy_e"]), np.isfinite(mg["mean_energy_e"]))
+            rel = np.abs(mg["mean_energy_e"][both] - mo["mean_energy_e"][both]) / np.maximum(mo["mean_energy_e"][both], 1e-3)
+            assert rel.max(initial=0) <= 2e-3
+        c = d.counters()
+        assert c["numax_violations"] == (0, 0)
+        log(f"  births over checkpoints: {total_births}")
+
+
+def test_gauss_law_and_charge_bookkeeping():
+    disc = W.small_argon(seed=11)
+    log("gauss/charge bookkeeping")
+    with B.Discharge(disc) as d:
+        from oracle.constants import E0, EPS0
+        W_ = d.derived()["W"]
+        for k in range(6):
+            d.step(57)
+            c = d.counters()
+            f = d.fields()
+            ne, ni = c["n_alive"]
+            assert np.isclose(f["Q"].sum(), E0 * W_ * (ni - ne), rtol=1e-6, atol=1e-6 * E0 * W_ * (ni + ne))
+            assert abs(c["sigma0"] + c["sigmad"] + f["Q"].sum()) <= 1e-9 * np.abs(f["Q"]).sum() + 1e-30
+            assert c["n_slots"][0] >= ne and c["n_slots"][1] >= ni
+            p0 = d.particles(0)
+            assert len(p0["x"]) == ne
+            assert np.all((p0["x"] > 0) & (p0["x"] < disc.gap_m))
+        # every step counted the particles alive at its start
+        assert c["step"] == 6 * 57
+        assert c["particle_steps"] > 0
+
+
+def test_sort_does_not_change_results():
+    """Order-independence: the cell sort only permutes storage; a few steps with and without
+    sorting agree per id within the single-step tolerance."""
+    base = W.small_argon(seed=2)
+    log("sort invariance")
+    out = []
+    for se in (0, 1):
+        with B.Discharge(base.replace(sort_every=se)) as d:
+            d.step(3)
+            out.append([d.particles(s) for s in (0, 1)] + [d.counters()])
+    for s in (0, 1):
+        a, b = out[0][s], out[1][s]
+        ka, kb = np.argsort(a["id"]), np.argsort(b["id"])
+        assert np.array_equal(a["id"][ka], b["id"][kb])
+        assert np.max(np.abs(a["x"][ka] - b["x"][kb])) <= REL_X * base.gap_m
+    assert out[0][2]["n_alive"] == out[1][2]["n_alive"]
+    assert out[1][2]["n_slots"] == out[1][2]["n_alive"]   # compacted after the last sort
