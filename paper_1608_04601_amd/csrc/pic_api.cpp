@@ -352,7 +352,7 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         size_t ntab = 0;
         for (const pic_xsec& p : h->xs) ntab += (size_t)p.n_points;
         float* tab = nullptr;
-        if (!dev_alloc(h, &P.ctrl, 1) || !dev_alloc(h, &P.E, nn) || !dev_alloc(h, &P.Q, nn) ||
+        if (!dev_alloc(h, &P.ctrl, 1) || !dev_alloc(h, &P.E, nn) || !dev_alloc(h, &P.Qi, nn) ||
             !dev_alloc(h, &P.Q_last, nn) || !dev_alloc(h, &P.phi, nn) || !dev_alloc(h, &P.mom, (size_t)5 * nn) ||
             !dev_alloc(h, &P.birth_parent, (size_t)c.max_births_per_step) || !dev_alloc(h, &tab, std::max<size_t>(ntab, 1)) ||
             !dev_alloc(h, &h->sort_cnt, (size_t)2 * nc) || !dev_alloc(h, &h->sort_cursor, (size_t)2 * nc))
@@ -408,7 +408,7 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         // launch shape: one workgroup per contiguous particle range; LDS holds the node
         // field, the private charge grid and the four moment grids
         h->threads = nn <= 1025 ? 256 : 1024;
-        const size_t pass_lds = 32 * 4 + (size_t)4 * nn * 6;
+        const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 4 + 16);
         const size_t epi_lds = (size_t)(2 * nn + 18) * 8;
         const size_t birth_lds = (size_t)pic::kBirthSortCap * 4;
         h->lds = std::max(pass_lds, std::max(epi_lds, birth_lds));
@@ -434,7 +434,7 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         }
         c0.period_valid = 1;
         if (!hip_ok(h, hipMemcpyAsync(P.ctrl, &c0, sizeof(c0), hipMemcpyHostToDevice, h->stream), "upload ctrl") ||
-            !hip_ok(h, hipMemsetAsync(P.Q, 0, nn * sizeof(double), h->stream), "zero Q") ||
+            !hip_ok(h, hipMemsetAsync(P.Qi, 0, nn * sizeof(unsigned long long), h->stream), "zero Q") ||
             !hip_ok(h, hipMemsetAsync(P.mom, 0, 5 * nn * sizeof(double), h->stream), "zero moments") ||
             !hip_ok(h, hipMemsetAsync(h->sort_cnt, 0, 2 * nc * sizeof(unsigned), h->stream), "zero sort counts"))
             goto fail_init;
@@ -648,7 +648,8 @@ int pic_set_particles(pic_handle* h, int species, const double* x, const float* 
     c.next_id[species] = next_id == 0 ? 0 : (int64_t)next_id;
     c.step = step;
     if (!hip_ok(h, hipMemcpy(h->P.ctrl, &c, sizeof(c), hipMemcpyHostToDevice), "write ctrl")) return h->status;
-    if (!hip_ok(h, hipMemset(h->P.Q, 0, (h->cfg.n_cells + 1) * sizeof(double)), "zero Q")) return h->status;
+    if (!hip_ok(h, hipMemset(h->P.Qi, 0, (h->cfg.n_cells + 1) * sizeof(unsigned long long)), "zero Q"))
+        return h->status;
     if (launch_pass_timed(h, pic::kDeposit)) return h->status;
     return check_device(h);
 }

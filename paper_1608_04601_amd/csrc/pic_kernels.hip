@@ -12,7 +12,9 @@
 // Particles are FP32 structure-of-arrays streamed once per step with coalesced loads;
 // vy, vz are read only by collision candidates (and electrons on moment steps) and
 // written only after a real collision.  Deposits go to a workgroup-private FP32 copy of
-// the grid in LDS and are flushed to the FP64 grid with one atomic per touched node.
+// the grid in LDS and are flushed to the global grid with one atomic per touched node.
+// The charge grid is fixed point (integer weights summing to 2^24 per particle): exact,
+// and independent of the order in which lanes and workgroups add to it.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -95,6 +97,14 @@ __device__ __forceinline__ void lds_add2(float* a, int j, float w, float v) {
     atomicAdd(&a[j + 1], v * w);
 }
 
+// Charge of one particle (sign q = +-1) to nodes j, j+1 in fixed point.
+__device__ __forceinline__ void lds_charge(unsigned long long* a, int j, float w, int q) {
+    const long long wq = (long long)__float2int_rn(w * kQScale);   // in [0, 2^24]
+    const long long total = (long long)kQScale;
+    atomicAdd(&a[j], (unsigned long long)(q * (total - wq)));
+    atomicAdd(&a[j + 1], (unsigned long long)(q * wq));
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_agent(const T* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -105,8 +115,8 @@ enum : int { kCntAbs = 0, kCntColl = 4, kCntViol = 20, kCntErr = 22, kCntLast = 
 
 struct Lds {
     uint32_t* cnt;
+    unsigned long long* Q;   // fixed-point charge
     float* E;
-    float* Q;
     float* M;   // 4 x nn moment sums: dens_e, dens_i, energy_e, flux_i
 };
 
@@ -116,7 +126,7 @@ __device__ __forceinline__ float absorb_or_deposit(const Params& P, const Lds& L
         int j;
         float w;
         cell_of(x, P.n_cells, j, w);
-        lds_add2(L.Q, j, w, s ? 1.0f : -1.0f);
+        lds_charge(L.Q, j, w, s ? 1 : -1);
         return x;
     }
     if (x <= 0.0f)
@@ -158,7 +168,7 @@ __device__ __forceinline__ void particle(const Params& P, const Lds& L, int s, i
         int j;
         float w;
         cell_of(x, P.n_cells, j, w);
-        lds_add2(L.Q, j, w, s ? 1.0f : -1.0f);
+        lds_charge(L.Q, j, w, s ? 1 : -1);
         return;
     }
     float* __restrict__ VX = P.vx[cur][s];
@@ -351,9 +361,9 @@ __device__ void solve_field(const Params& P, double* sd, double phi0, double& E0
     double* scratch = sd + 2 * nn;   // 16 + 2
     const double dxe = P.dx_d / P.eps0;
     for (int i = tid; i < nn; i += nt) {
-        const double q = ld_agent(&P.Q[i]) * P.e0W;
+        const double q = (double)(long long)ld_agent(&P.Qi[i]) * (kQScaleInv * P.e0W);
         P.Q_last[i] = q;
-        P.Q[i] = 0.0;
+        P.Qi[i] = 0ull;
         work[i] = (i >= 1 && i < nc) ? q : 0.0;
         if (i == 0) scratch[16] = q;
         if (i == nc) scratch[17] = q;
@@ -544,9 +554,9 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     Ctrl* C = P.ctrl;
     Lds L;
     L.cnt = reinterpret_cast<uint32_t*>(smem);
-    L.E = reinterpret_cast<float*>(smem + kCntSlots * 4);
-    L.Q = L.E + nn;
-    L.M = L.Q + nn;
+    L.Q = reinterpret_cast<unsigned long long*>(smem + kCntSlots * 4);
+    L.E = reinterpret_cast<float*>(L.Q + nn);
+    L.M = L.E + nn;
 
     const int64_t step = C->step;
     const unsigned cur = C->cur;
@@ -557,7 +567,7 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     for (int i = tid; i < kCntSlots; i += nt) L.cnt[i] = 0;
     for (int i = tid; i < nn; i += nt) {
         L.E[i] = (MODE == kDeposit) ? 0.0f : P.E[i];
-        L.Q[i] = 0.0f;
+        L.Q[i] = 0ull;
     }
     if (sample)
         for (int i = tid; i < 4 * nn; i += nt) L.M[i] = 0.0f;
@@ -574,8 +584,8 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     __syncthreads();
 
     for (int i = tid; i < nn; i += nt) {
-        const float q = L.Q[i];
-        if (q != 0.0f) unsafeAtomicAdd(&P.Q[i], (double)q);
+        const unsigned long long q = L.Q[i];
+        if (q != 0ull) atomicAdd(&P.Qi[i], q);
     }
     if (sample)
         for (int i = tid; i < 4 * nn; i += nt) {

@@ -12,6 +12,11 @@ namespace pic {
 constexpr int kMaxProc = 16;
 constexpr int kMaxCells = 4096;
 constexpr int kBirthSortCap = 2048;   // births per step ranked in LDS; more take a slow path
+// Charge deposit in fixed point: a particle's two cloud-in-cell weights are integers
+// summing to 2^24, accumulated with integer atomics, so the node charges are exact and
+// independent of the order of accumulation (bitwise reproducible runs).
+constexpr float kQScale = 16777216.0f;
+constexpr double kQScaleInv = 1.0 / 16777216.0;
 
 // particle-pass modes (bit set)
 constexpr int kComplete = 1;   // finish the previous step: second half kick, MCC, births, moments
@@ -77,7 +82,7 @@ struct Params {
     int64_t cap[2];
     Ctrl* ctrl;
     float* E;            // node field, FP32 copy for the gather [nn]
-    double* Q;           // node charge accumulator, units of W e0 [nn]
+    unsigned long long* Qi;  // node charge accumulator, signed fixed point: 2^24 per particle [nn]
     double* Q_last;      // charge of the last solve [C/m^2] [nn]
     double* phi;         // node potential [V] [nn]
     double* mom;         // moment window sums [5][nn]: dens_e, dens_i, energy_e, flux_i, phi

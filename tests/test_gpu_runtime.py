@@ -1,0 +1,118 @@
+"""Runtime behaviour through the C ABI on the GPU: deferred device errors and the poisoned
+handle (forced from the host with tiny capacities, so every kernel still exits normally),
+host-side argument checks, determinism of a seeded run, and checkpoint/resume through the
+particle hooks."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import log
+from paper_1608_04601_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+def _ionising(n=4000, seed=0):
+    """Argon-like discharge with a large ionisation cross section and hot electrons, so that
+    births happen from the first steps."""
+    top = 200.0
+    procs = (W.Process(W.E_ELASTIC, 0, 0.0, 0.1, 0.0, W.constant_table(1e-19, top, 0.1)),
+             W.Process(W.E_IONIZATION, 0, 15.8, 0.1, 0.0, W.ramp_table(15.8, 3e-19, top, 0.1)),
+             W.Process(W.I_BACKWARD, 0, 0.0, 0.1, 0.0, W.constant_table(5e-19, top, 0.1)))
+    return W.small_argon(seed=seed, n_super=n).replace(processes=procs, te_init_eV=20.0)
+
+
+def test_capacity_overflow_is_deferred_and_poisons():
+    disc = _ionising().replace(capacity=(4000, 4000))
+    log("capacity overflow")
+    d = B.Discharge(disc)
+    try:
+        d.step(5)   # returns without waiting; the device raises the error flag
+        with pytest.raises(B.PicError) as e:
+            d.sync()
+        assert e.value.status == B.PIC_ECAPACITY
+        assert "storage" in str(e.value)
+        # poisoned: every later call returns the first error
+        for call in (lambda: d.step(1), d.sync, d.counters, lambda: d.particles(0)):
+            with pytest.raises(B.PicError) as e2:
+                call()
+            assert e2.value.status == B.PIC_ECAPACITY
+    finally:
+        d.close()
+
+
+def test_birth_buffer_overflow():
+    disc = _ionising().replace(max_births_per_step=1)
+    log("birth buffer overflow")
+    with B.Discharge(disc) as d:
+        d.step(10)
+        with pytest.raises(B.PicError) as e:
+            d.sync()
+        assert e.value.status == B.PIC_ECAPACITY and "birth" in str(e.value)
+
+
+def test_births_within_capacity_are_counted():
+    disc = _ionising()
+    with B.Discharge(disc) as d:
+        d.step(10)
+        c = d.counters()
+        assert c["births_total"] > 0
+        assert c["next_id"][0] == disc.n_super[0] + c["births_total"]
+        assert c["next_id"][1] == disc.n_super[1] + c["births_total"]
+        ids = d.particles(0)["id"]
+        assert len(np.unique(ids)) == len(ids) and ids.max() < c["next_id"][0]
+
+
+def test_set_particles_rejects_bad_input():
+    disc = W.small_argon(n_super=1000)
+    with B.Discharge(disc) as d:
+        p = d.particles(0)
+        bad_x = p["x"].copy()
+        bad_x[3] = disc.gap_m * 1.5
+        with pytest.raises(B.PicError) as e:
+            B.pic_set_particles(d.h, 0, bad_x, p["vx"], p["vy"], p["vz"], p["id"], 1000, 0)
+        assert e.value.status == B.PIC_EINVAL
+
+
+def _same_state(a, b):
+    """Bitwise equality per id (the charge deposit is exact fixed point, so the run does not
+    depend on storage order, workgroup count or atomic ordering)."""
+    ka, kb = np.argsort(a["id"]), np.argsort(b["id"])
+    assert np.array_equal(a["id"][ka], b["id"][kb])
+    for key in ("x", "vx", "vy", "vz"):
+        assert np.array_equal(a[key][ka], b[key][kb]), key
+
+
+def test_seeded_run_is_reproducible():
+    disc = W.small_argon(seed=4)
+    runs = []
+    for blocks in (0, 7):
+        with B.Discharge(disc, launch_blocks=blocks) as d:
+            d.step(300)
+            runs.append((d.particles(0), d.particles(1), d.counters()))
+    for s in (0, 1):
+        _same_state(runs[0][s], runs[1][s])
+    assert runs[0][2]["collisions"].tolist() == runs[1][2]["collisions"].tolist()
+    assert runs[0][2]["next_id"] == runs[1][2]["next_id"]
+
+
+def test_checkpoint_resume_equals_continuous_run():
+    disc = W.small_argon(seed=6)
+    with B.Discharge(disc) as d:
+        d.step(40)
+        snap = [d.particles(s) for s in (0, 1)]
+        c = d.counters()
+        d.step(30)
+        cont = [d.particles(s) for s in (0, 1)]
+        fc = d.fields()
+    with B.Discharge(disc) as r:
+        for s in (0, 1):
+            p = snap[s]
+            B.pic_set_particles(r.h, s, p["x"], p["vx"], p["vy"], p["vz"], p["id"], c["next_id"][s], c["step"])
+        r.step(30)
+        res = [r.particles(s) for s in (0, 1)]
+        fr = r.fields()
+        assert r.counters()["step"] == 70
+    for s in (0, 1):
+        _same_state(cont[s], res[s])
+    assert np.array_equal(fc["E"], fr["E"])
