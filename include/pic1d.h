@@ -159,8 +159,8 @@ typedef struct pic_handle pic_handle;
 
 /* Validate cfg, derive the constants, allocate device storage, load the uniform
  * Maxwellian initial state (Sec. 2.2) and solve the field at t = 0.  hip_stream is a
- * hipStream_t on the current device, or NULL for a stream the library creates.  The
- * handle keeps the stream; the caller keeps it alive until pic_free.  On error *out is
+ * hipStream_t on the current device, or NULL for the device's null stream; all work of the
+ * handle is ordered on it, and the caller keeps it alive until pic_free.  On error *out is
  * NULL and the status says why (pic_last_error(NULL) gives the message). */
 int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out);
 

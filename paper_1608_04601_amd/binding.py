@@ -145,7 +145,8 @@ class Config:
 
 # ---------------------------------------------------------------------------- entry points
 def pic_init(config: Config, stream=None):
-    """Returns the opaque handle (c_void_p).  stream: a hipStream_t as int, or None."""
+    """Returns the opaque handle (c_void_p).  stream: a hipStream_t as int; 0 or None is the
+    null stream (torch's default stream on ROCm)."""
     L = load_library()
     h = C.c_void_p()
     rc = L.pic_init(C.byref(config.c), C.c_void_p(stream) if stream else None, C.byref(h))

@@ -51,7 +51,6 @@ struct pic_handle {
     // device
     int device = 0;
     hipStream_t stream = nullptr;
-    bool own_stream = false;
     std::vector<void*> allocs;
     pic::Params P{};
     unsigned* sort_cnt = nullptr;
@@ -212,13 +211,11 @@ bool dev_alloc(pic_handle* h, T** out, size_t count) {
 }
 
 void release(pic_handle* h) {
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    (void)hipStreamSynchronize(h->stream);
     for (void* p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     h->ev.clear();
-    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
-    h->stream = nullptr;
 }
 
 int check_device(pic_handle* h) {
@@ -330,12 +327,7 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
 
     // ---- stream
     if (!hip_ok(h, hipGetDevice(&h->device), "hipGetDevice")) goto fail_init;
-    if (hip_stream) {
-        h->stream = static_cast<hipStream_t>(hip_stream);
-    } else {
-        if (!hip_ok(h, hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking), "hipStreamCreate")) goto fail_init;
-        h->own_stream = true;
-    }
+    h->stream = static_cast<hipStream_t>(hip_stream);   // NULL: the device's null stream
 
     {
         pic::Params& P = h->P;

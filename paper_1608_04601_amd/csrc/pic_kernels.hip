@@ -138,6 +138,89 @@ __device__ __forceinline__ float absorb_or_deposit(const Params& P, const Lds& L
     return -1.0f;   // hole marker
 }
 
+// After the drift, without depositing: returns x, or the hole marker after counting the
+// absorption (the caller deposits survivors wave-aggregated).
+__device__ __forceinline__ float absorb_only(const Params& P, const Lds& L, int s, float x) {
+    if (x > 0.0f && x < P.ncf) return x;
+    if (x <= 0.0f)
+        atomicAdd(&L.cnt[kCntAbs + 2 * s + 0], 1u);
+    else if (x >= P.ncf)
+        atomicAdd(&L.cnt[kCntAbs + 2 * s + 1], 1u);
+    else
+        atomicOr(&L.cnt[kCntErr], kErrNumeric);
+    return -1.0f;
+}
+
+extern "C" __device__ int __ockl_wfred_add_i32(int);
+extern "C" __device__ float __ockl_wfred_add_f32(float);
+
+// Wave-aggregated cloud-in-cell deposits.  Called by every lane of a wave in converged
+// control flow; a lane with t <= 0 contributes nothing.  When the wave's cells lie within
+// four consecutive cells of the first contributing lane (cell-sorted particles), the
+// contributions to each of the five nodes they touch are summed across the wave with DPP
+// reductions and one lane adds them to LDS; otherwise every lane adds its own.  The charge
+// is integer (fixed point), so the result is the same either way.
+__device__ __forceinline__ void wave_charge(unsigned long long* Q, int nc, float t, int q) {
+    const bool valid = t > 0.0f;
+    int j = 0;
+    float w = 0.0f;
+    if (valid) cell_of(t, nc, j, w);
+    const unsigned long long vm = __ballot(valid);
+    if (vm == 0ull) return;
+    const int lead = __builtin_ctzll(vm);
+    const int j0 = __shfl(j, lead, 64);
+    const bool far = valid && (j < j0 - 1 || j > j0 + 2);
+    if (__ballot(far) == 0ull) {
+        const int wq = valid ? __float2int_rn(w * kQScale) : 0;
+        const int tot = valid ? (int)kQScale : 0;
+        const bool first = (int)(threadIdx.x & 63) == lead;
+#pragma unroll
+        for (int d = -1; d <= 3; ++d) {
+            const int n = j0 + d;
+            const int c = (j == n ? tot - wq : 0) + (j == n - 1 ? wq : 0);
+            const int sum = __ockl_wfred_add_i32(c);   // |sum| <= 64 * 2^24
+            if (first && sum != 0) atomicAdd(&Q[n], (unsigned long long)(long long)(q * sum));
+        }
+    } else if (valid) {
+        lds_charge(Q, j, w, q);
+    }
+}
+
+// Moment sample (density weight and a second quantity m2) of species s, wave-aggregated
+// the same way (FP32 sums; moments do not feed back into the dynamics).
+__device__ __forceinline__ void wave_moments(float* M, int nn, int nc, int s, float t, float m2) {
+    float* dens = M + (s ? nn : 0);
+    float* sec = M + (s ? 3 * nn : 2 * nn);
+    const bool valid = t > 0.0f;
+    int j = 0;
+    float w = 0.0f;
+    if (valid) cell_of(t, nc, j, w);
+    const unsigned long long vm = __ballot(valid);
+    if (vm == 0ull) return;
+    const int lead = __builtin_ctzll(vm);
+    const int j0 = __shfl(j, lead, 64);
+    const bool far = valid && (j < j0 - 1 || j > j0 + 2);
+    if (__ballot(far) == 0ull) {
+        const bool first = (int)(threadIdx.x & 63) == lead;
+        const float a = valid ? 1.0f - w : 0.0f, b = valid ? w : 0.0f;
+#pragma unroll
+        for (int d = -1; d <= 3; ++d) {
+            const int n = j0 + d;
+            const float c = (j == n ? a : 0.0f) + (j == n - 1 ? b : 0.0f);
+            const float cs = c * m2;
+            const float sd = __ockl_wfred_add_f32(c);
+            const float ss = __ockl_wfred_add_f32(cs);
+            if (first && sd != 0.0f) {
+                atomicAdd(&dens[n], sd);
+                atomicAdd(&sec[n], ss);
+            }
+        }
+    } else if (valid) {
+        lds_add2(dens, j, w, 1.0f);
+        lds_add2(sec, j, w, m2);
+    }
+}
+
 __device__ __forceinline__ void sample_moments(const Params& P, const Lds& L, int s, float x, float vx,
                                                float v2) {
     const int nn = P.n_cells + 1;
@@ -153,47 +236,46 @@ __device__ __forceinline__ void sample_moments(const Params& P, const Lds& L, in
     }
 }
 
-// One particle of species s in slot i.
-template <int MODE>
-__device__ __forceinline__ void particle(const Params& P, const Lds& L, int s, int64_t i, uint32_t stepf,
-                                         unsigned cur, int64_t ns0, int64_t ns1, bool sample) {
-    float* __restrict__ X = P.x[cur][s];
-    float x = X[i];
+// One particle of species S in slot i, whose x, vx (and id; and, for electrons on completing
+// launches, vy, vz) were loaded by the caller.
+// On return, tq is the position to deposit as charge (<= 0: none) and tm, m2 the position
+// and second quantity of the moment sample (tm <= 0: none); the caller deposits both
+// wave-aggregated.
+template <int MODE, int S>
+__device__ __forceinline__ void particle(const Params& P, const Lds& L, int64_t i, float x, float vx, uint32_t pid,
+                                         float vy, float vz, uint32_t stepf, unsigned cur, int64_t ns0,
+                                         int64_t ns1, bool sample, float& tq, float& tm, float& m2) {
+    tq = -1.0f;
+    tm = -1.0f;
+    m2 = 0.0f;
     if (!(x > 0.0f)) {   // hole (or a corrupted coordinate)
         if (x != x) atomicOr(&L.cnt[kCntErr], kErrNumeric);
-        if ((MODE & kComplete) && P.dec[s]) P.dec[s][i] = 0;
+        if ((MODE & kComplete) && P.dec[S]) P.dec[S][i] = 0;
         return;
     }
     if (MODE == kDeposit) {
-        int j;
-        float w;
-        cell_of(x, P.n_cells, j, w);
-        lds_charge(L.Q, j, w, s ? 1 : -1);
+        tq = x;
         return;
     }
-    float* __restrict__ VX = P.vx[cur][s];
-    float vx = VX[i];
     int j;
     float w;
     cell_of(x, P.n_cells, j, w);
     const float E = fmaf(w, L.E[j + 1] - L.E[j], L.E[j]);   // cloud-in-cell gather
-    const float kE = P.kick[s] * E;                          // half kick, Sec. 2.5 Verlet
-    float vy = 0.0f, vz = 0.0f;
+    const float kE = P.kick[S] * E;                          // half kick, Sec. 2.5 Verlet
     bool dirty = false;
 
     if (MODE & kComplete) {
         vx += kE;   // v^n
-        const uint32_t pid = P.id[cur][s][i];
-        const uint4 A = philox(pid, 0u, stepf, ((uint32_t)s << 8) | kCollision, P.key0, P.key1);
+        const uint4 A = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kCollision, P.key0, P.key1);
         int8_t code = 0;
-        bool have_yz = false;
-        if ((A.x >> 8) < P.T[s]) {   // null-collision candidate (integer test)
+        if ((A.x >> 8) < P.T[S]) {   // null-collision candidate (integer test)
             code = 1;
-            vy = P.vy[cur][s][i];
-            vz = P.vz[cur][s][i];
-            have_yz = true;
+            if (S == 1) {            // ions read vy, vz only when they are candidates
+                vy = P.vy[cur][1][i];
+                vz = P.vz[cur][1][i];
+            }
             float vtx = 0.0f, vty = 0.0f, vtz = 0.0f;
-            if (s == 1) {   // gas atom from the Maxwellian at T_gas
+            if (S == 1) {   // gas atom from the Maxwellian at T_gas
                 const uint4 B = philox(pid, 0u, stepf, (1u << 8) | kTarget, P.key0, P.key1);
                 float z0, z1, z2, z3;
                 normal2(B.x, B.y, z0, z1);
@@ -205,37 +287,37 @@ __device__ __forceinline__ void particle(const Params& P, const Lds& L, int s, i
             const float gx = vx - vtx, gy = vy - vty, gz = vz - vtz;
             const float g2 = gx * gx + gy * gy + gz * gz;
             const float gm = sqrtf(g2);
-            const float R = u01(A.y) * P.numax[s];
+            const float R = u01(A.y) * P.numax[S];
             float c = 0.0f;
             int sel = -1;
             for (int q = 0; q < P.nproc; ++q) {
                 const ProcDev& p = P.proc[q];
-                if (p.species != s) continue;
+                if (p.species != S) continue;
                 c = fmaf(nsigma(p, P.tab, p.efac * g2), gm, c);
                 if (sel < 0 && R < c) sel = q;
             }
-            if (c > P.numax[s]) atomicAdd(&L.cnt[kCntViol + s], 1u);
+            if (c > P.numax[S]) atomicAdd(&L.cnt[kCntViol + S], 1u);
             if (sel >= 0) {
                 code = (int8_t)(2 + sel);
                 atomicAdd(&L.cnt[kCntColl + sel], 1u);
                 const ProcDev& p = P.proc[sel];
-                const uint4 Cw = philox(pid, 0u, stepf, ((uint32_t)s << 8) | kScatter, P.key0, P.key1);
+                const uint4 Cw = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kScatter, P.key0, P.key1);
                 float n1x, n1y, n1z;
                 iso_dir(Cw.x, Cw.y, n1x, n1y, n1z);
                 dirty = true;
                 if (p.kind == 0 || p.kind == 3) {   // elastic / isotropic: CM-isotropic two-body
-                    const float fa = P.fa[s], fb = P.fb[s];
+                    const float fa = P.fa[S], fb = P.fb[S];
                     const float sgb = fb * gm;
                     vx = fmaf(sgb, n1x, fmaf(fa, vx, fb * vtx));
                     vy = fmaf(sgb, n1y, fmaf(fa, vy, fb * vty));
                     vz = fmaf(sgb, n1z, fmaf(fa, vz, fb * vtz));
-                } else if (p.kind == 1) {   // excitation: lose the threshold energy
+                } else if (S == 0 && p.kind == 1) {   // excitation: lose the threshold energy
                     const float eps = P.half_m_over_e[0] * g2;
                     const float sp = sqrtf(fmaxf(eps - p.thr, 0.0f) * P.two_e_over_m_e);
                     vx = sp * n1x;
                     vy = sp * n1y;
                     vz = sp * n1z;
-                } else if (p.kind == 2) {   // ionisation: equal share of eps - eps_iz
+                } else if (S == 0 && p.kind == 2) {   // ionisation: equal share of eps - eps_iz
                     const float eps = P.half_m_over_e[0] * g2;
                     const float sp = sqrtf(fmaxf(eps - p.thr, 0.0f) * P.e_over_m_e);
                     vx = sp * n1x;
@@ -243,14 +325,14 @@ __device__ __forceinline__ void particle(const Params& P, const Lds& L, int s, i
                     vz = sp * n1z;
                     float n2x, n2y, n2z;
                     iso_dir(Cw.z, Cw.w, n2x, n2y, n2z);
-                    const uint4 D = philox(pid, 0u, stepf, ((uint32_t)s << 8) | kNewIon, P.key0, P.key1);
+                    const uint4 D = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kNewIon, P.key0, P.key1);
                     float y0, y1, y2, y3;
                     normal2(D.x, D.y, y0, y1);
                     normal2(D.z, D.w, y2, y3);
                     const unsigned k = atomicAdd(&P.ctrl->n_births, 1u);
                     if ((int)k < P.max_births && ns0 + (int64_t)k < P.cap[0] && ns1 + (int64_t)k < P.cap[1]) {
                         P.birth_parent[k] = pid;
-                        // children at the parent's position x^n with end-of-step velocities
+                        // products at the parent's position x^n with end-of-step velocities
                         float cev[3] = {sp * n2x, sp * n2y, sp * n2z};
                         float civ[3] = {P.vT * y0, P.vT * y1, P.vT * y2};
                         if (sample) {
@@ -284,28 +366,60 @@ __device__ __forceinline__ void particle(const Params& P, const Lds& L, int s, i
                 }
             }
         }
-        if (P.dec[s]) P.dec[s][i] = code;
+        if (P.dec[S]) P.dec[S][i] = code;
         if (sample) {
-            float v2 = 0.0f;
-            if (s == 0) {
-                if (!have_yz) {
-                    vy = P.vy[cur][s][i];
-                    vz = P.vz[cur][s][i];
-                }
-                v2 = vx * vx + vy * vy + vz * vz;
-            }
-            sample_moments(P, L, s, x, vx, v2);
+            tm = x;
+            m2 = S == 0 ? P.half_m_over_e[0] * (vx * vx + vy * vy + vz * vz) : vx;
         }
     }
     if (MODE & kAdvance) {
         vx += kE;                                  // v^{n+1/2}
-        x = absorb_or_deposit(P, L, s, fmaf(vx, P.dt_over_dx, x));
-        X[i] = x;
+        x = absorb_only(P, L, S, fmaf(vx, P.dt_over_dx, x));
+        tq = x;
+        P.x[cur][S][i] = x;
     }
-    VX[i] = vx;
+    P.vx[cur][S][i] = vx;
     if (dirty) {
-        P.vy[cur][s][i] = vy;
-        P.vz[cur][s][i] = vz;
+        P.vy[cur][S][i] = vy;
+        P.vz[cur][S][i] = vz;
+    }
+}
+
+// Particles [begin, end) of species S, kBatch per thread with all their loads issued first.
+constexpr int kBatch = 4;
+
+template <int MODE, int S>
+__device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t begin, int64_t end, uint32_t stepf,
+                                          unsigned cur, int64_t ns0, int64_t ns1, bool sample) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const float* __restrict__ X = P.x[cur][S];
+    const float* __restrict__ VX = P.vx[cur][S];
+    const uint32_t* __restrict__ ID = P.id[cur][S];
+    const float* __restrict__ VY = P.vy[cur][S];
+    const float* __restrict__ VZ = P.vz[cur][S];
+    constexpr bool kPreloadYZ = (MODE & kComplete) && S == 0;
+    for (int64_t base = begin; base < end; base += (int64_t)nt * kBatch) {
+        float x[kBatch], vx[kBatch], vy[kBatch], vz[kBatch];
+        uint32_t id[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int64_t i = base + (int64_t)u * nt + tid;
+            const bool in = i < end;
+            x[u] = in ? X[i] : -1.0f;
+            vx[u] = (MODE != kDeposit && in) ? VX[i] : 0.0f;
+            id[u] = ((MODE & kComplete) && in) ? ID[i] : 0u;
+            vy[u] = (kPreloadYZ && in) ? VY[i] : 0.0f;
+            vz[u] = (kPreloadYZ && in) ? VZ[i] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int64_t i = base + (int64_t)u * nt + tid;
+            float tq = -1.0f, tm = -1.0f, m2 = 0.0f;
+            if (i < end)
+                particle<MODE, S>(P, L, i, x[u], vx[u], id[u], vy[u], vz[u], stepf, cur, ns0, ns1, sample, tq, tm, m2);
+            wave_charge(L.Q, P.n_cells, tq, S ? 1 : -1);
+            if (sample) wave_moments(L.M, P.n_cells + 1, P.n_cells, S, tm, m2);
+        }
     }
 }
 
@@ -573,14 +687,33 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
         for (int i = tid; i < 4 * nn; i += nt) L.M[i] = 0.0f;
     __syncthreads();
 
-    const int64_t total = ns0 + ns1;
-    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-    const int64_t begin = (int64_t)blockIdx.x * per;
-    const int64_t end = min(begin + per, total);
-    for (int64_t v = begin + tid; v < end; v += nt) {
-        const int s = v >= ns0;
-        particle<MODE>(P, L, s, s ? v - ns0 : v, stepf, cur, ns0, ns1, sample);
+    // Workgroups are species-pure: the first G_e take the electrons, the rest the ions, in
+    // proportion to the slot counts (a single workgroup takes both).
+    const int G = gridDim.x;
+    int64_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+    if (G == 1) {
+        e0 = ns0;
+        e1 = ns1;
+    } else {
+        const int64_t total = ns0 + ns1;
+        int Ge = total > 0 ? (int)(((double)G * (double)ns0) / (double)total + 0.5) : G / 2;
+        if (ns0 > 0) Ge = max(Ge, 1);
+        if (ns1 > 0) Ge = min(Ge, G - 1);
+        if (ns1 == 0) Ge = G;
+        const int b = blockIdx.x;
+        if (b < Ge) {
+            const int64_t per = (ns0 + Ge - 1) / Ge;
+            b0 = min((int64_t)b * per, ns0);
+            e0 = min(b0 + per, ns0);
+        } else {
+            const int Gi = G - Ge;
+            const int64_t per = (ns1 + Gi - 1) / Gi;
+            b1 = min((int64_t)(b - Ge) * per, ns1);
+            e1 = min(b1 + per, ns1);
+        }
     }
+    if (e0 > b0) run_range<MODE, 0>(P, L, b0, e0, stepf, cur, ns0, ns1, sample);
+    if (e1 > b1) run_range<MODE, 1>(P, L, b1, e1, stepf, cur, ns0, ns1, sample);
     __syncthreads();
 
     for (int i = tid; i < nn; i += nt) {
