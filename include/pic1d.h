@@ -91,7 +91,7 @@ typedef struct pic_config {
     double te_init_eV;          /* k_B T of the initial electron Maxwellian, >= 0      */
     double ti_init_eV;          /* k_B T of the initial ion Maxwellian, >= 0           */
     int32_t n_cells;            /* 2 .. PIC_MAX_CELLS cells, n_cells + 1 nodes         */
-    int32_t n_xsec;             /* 0 .. PIC_MAX_PROCESSES                              */
+    int32_t n_xsec;             /* 0 .. PIC_MAX_PROCESSES, at most 8 per species       */
     const pic_xsec* xsec;       /* host array of n_xsec tables, in selection order     */
     int64_t n_init_super[2];    /* initial particles per species; [0] > 0              */
     int64_t capacity[2];        /* storage per species, >= n_init_super, < 2^31        */

@@ -70,11 +70,19 @@ class pic_derived(C.Structure):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load libpic1d.so; raises if it has not been built (there is no fallback path)."""
+def load_library(path: str = None):
+    """Load libpic1d.so (LIB_PATH unless a path is given); raises if it has not been built
+    (there is no fallback path)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = LIB_PATH if path is None else path
+    try:
+        # torch ships its own HIP runtime under the same soname; loading it first keeps one
+        # runtime in the process, so stream handles passed in from torch are valid here
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1608_04601_amd.build`")
     L = C.CDLL(path)

@@ -22,6 +22,9 @@ def hipcc_path():
 
 def compile_flags():
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
+            # no implicit a*b+c contraction: the arithmetic is exactly as written (fused only
+            # where fmaf is spelled out), so results do not change with code layout
+            "-ffp-contract=off",
             # packed FP32 VALU forms are kept out of the generated code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

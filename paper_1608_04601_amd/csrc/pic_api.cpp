@@ -181,8 +181,12 @@ std::string validate(const pic_config* c) {
     if (c->moments_every < 1) return "moments_every must be >= 1";
     if (c->max_births_per_step < 1) return "max_births_per_step must be >= 1";
     if (c->launch_blocks < 0 || c->launch_blocks > 65536) return "launch_blocks must be in [0, 65536]";
+    int per_species[2] = {0, 0};
     for (int j = 0; j < c->n_xsec; ++j) {
         const pic_xsec& p = c->xsec[j];
+        if (p.kind >= PIC_E_ELASTIC && p.kind <= PIC_I_BACKWARD &&
+            ++per_species[species_of_kind(p.kind)] > pic::kMaxProcPerSpecies)
+            return "at most 8 processes per species";
         if (p.kind < PIC_E_ELASTIC || p.kind > PIC_I_BACKWARD) return "xsec kind out of range";
         if (p.frame != PIC_FRAME_LAB && p.frame != PIC_FRAME_CM) return "xsec frame out of range";
         if (p.n_points < 2 || p.n_points > (1 << 22)) return "xsec n_points must be in [2, 2^22]";
@@ -354,6 +358,10 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         htab.reserve(ntab);
         P.nproc = (int)h->xs.size();
         for (size_t j = 0; j < h->xs.size(); ++j) {
+            const int s = species_of_kind(h->xs[j].kind);
+            P.sp_idx[s][P.sp_n[s]++] = (int)j;
+        }
+        for (size_t j = 0; j < h->xs.size(); ++j) {
             const pic_xsec& p = h->xs[j];
             pic::ProcDev& d = P.proc[j];
             const int s = species_of_kind(p.kind);
@@ -396,14 +404,18 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         P.V0 = c.rf_voltage_V;
         P.omega = 2.0 * kPi * c.rf_frequency_Hz;
         P.dt_d = c.dt_s;
+        P.mscale[0] = pic::kMomScaleE;
+        P.mscale[1] = pic::kMomScaleI;
 
         // launch shape: one workgroup per contiguous particle range; LDS holds the node
         // field, the private charge grid and the four moment grids
         h->threads = nn <= 1025 ? 256 : 1024;
-        const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 4 + 16);
-        const size_t epi_lds = (size_t)(2 * nn + 18) * 8;
-        const size_t birth_lds = (size_t)pic::kBirthSortCap * 4;
-        h->lds = std::max(pass_lds, std::max(epi_lds, birth_lds));
+        // counters, fixed-point charge, two fixed-point moment sums, field, candidate queue
+        // (1.5 x threads entries of seven words)
+        const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 16 + 4) + (size_t)(h->threads + h->threads / 2) * 7 * 4;
+        // last workgroup: control block copy, three FP64 node arrays, scratch, birth keys
+        const size_t epi_lds = 512 + (size_t)24 * nn + 256 + (size_t)pic::kBirthSortCap * 4;
+        h->lds = std::max(pass_lds, epi_lds);
         const int64_t total = c.n_init_super[0] + c.n_init_super[1];
         if (c.launch_blocks > 0) {
             h->blocks = c.launch_blocks;

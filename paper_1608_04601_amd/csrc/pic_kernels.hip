@@ -73,28 +73,10 @@ __device__ __forceinline__ void iso_dir(uint32_t a, uint32_t b, float& nx, float
     nz = sn * sp;
 }
 
-// n_gas * sigma_j(eps) [1/m]: zero below threshold, floor emin, clamp at the last point,
-// linear interpolation in between.
-__device__ __forceinline__ float nsigma(const ProcDev& p, const float* __restrict__ tab, float eps) {
-    if (eps < p.thr) return 0.0f;
-    const float t = fmaxf(eps, p.emin) * p.inv_de;
-    if (t >= (float)(p.n - 1)) return tab[p.off + p.n - 1];
-    const int k = (int)t;
-    const float f = t - (float)k;
-    const float a = tab[p.off + k];
-    const float b = tab[p.off + k + 1];
-    return fmaf(b - a, f, a);
-}
-
 // Cloud-in-cell cell and weight of a position t > 0 in cell units (both exact).
 __device__ __forceinline__ void cell_of(float t, int nc, int& j, float& w) {
     j = min((int)t, nc - 1);
     w = t - (float)j;
-}
-
-__device__ __forceinline__ void lds_add2(float* a, int j, float w, float v) {
-    atomicAdd(&a[j], v - v * w);
-    atomicAdd(&a[j + 1], v * w);
 }
 
 // Charge of one particle (sign q = +-1) to nodes j, j+1 in fixed point.
@@ -110,14 +92,41 @@ __device__ __forceinline__ T ld_agent(const T* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// LDS counter slots of one workgroup
-enum : int { kCntAbs = 0, kCntColl = 4, kCntViol = 20, kCntErr = 22, kCntLast = 31, kCntSlots = 32 };
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
+// Everything one workgroup hands to the last workgroup of a launch travels through
+// device-scope atomics (read back with device-scope atomic loads), so publishing it needs
+// only the completion of this wave's memory operations, not a release fence: an
+// agent-scope release would write back and invalidate the whole L2 of the XCD, once per
+// workgroup per step.
+__device__ __forceinline__ void wait_memory_complete() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// LDS counter slots of one workgroup
+enum : int { kCntAbs = 0, kCntColl = 4, kCntViol = 20, kCntErr = 22, kCntQueue = 23, kCntLast = 31, kCntSlots = 32 };
+
+// LDS of one workgroup of the particle pass.  A workgroup handles one species at a time:
+// M holds that species' two moment sums (density weight; electron energy or ion v_x).
+// Collision candidates wait in a queue (structure of arrays, 1.5 x blockDim entries) until
+// more than half a workgroup of them can be processed together.
 struct Lds {
     uint32_t* cnt;
     unsigned long long* Q;   // fixed-point charge
     float* E;
-    float* M;   // 4 x nn moment sums: dens_e, dens_i, energy_e, flux_i
+    unsigned long long* M;   // 2 x nn, fixed point
+    uint32_t* qslot;
+    uint32_t* qid;
+    uint32_t* qr;            // second Philox word of the collision draw
+    float* qx;
+    float* qvx;
+    float* qvy;
+    float* qvz;
 };
 
 // After the drift: absorb at the electrodes (Sec. 2.5, ties absorbed) or deposit.
@@ -152,7 +161,7 @@ __device__ __forceinline__ float absorb_only(const Params& P, const Lds& L, int 
 }
 
 extern "C" __device__ int __ockl_wfred_add_i32(int);
-extern "C" __device__ float __ockl_wfred_add_f32(float);
+extern "C" __device__ long __ockl_wfred_add_i64(long);
 
 // Wave-aggregated cloud-in-cell deposits.  Called by every lane of a wave in converged
 // control flow; a lane with t <= 0 contributes nothing.  When the wave's cells lie within
@@ -186,15 +195,31 @@ __device__ __forceinline__ void wave_charge(unsigned long long* Q, int nc, float
     }
 }
 
-// Moment sample (density weight and a second quantity m2) of species s, wave-aggregated
-// the same way (FP32 sums; moments do not feed back into the dynamics).
-__device__ __forceinline__ void wave_moments(float* M, int nn, int nc, int s, float t, float m2) {
-    float* dens = M + (s ? nn : 0);
-    float* sec = M + (s ? 3 * nn : 2 * nn);
+// Fixed-point split of a moment sample at cell weight w: density weights (2^24 - d1, d1)
+// and second quantity (s0, s1) with s0 + s1 = round(m2 * mscale).
+__device__ __forceinline__ void moment_parts(float w, float m2, double mscale, long long& d0, long long& d1,
+                                             long long& s0, long long& s1) {
+    d1 = (long long)__float2int_rn(w * kQScale);
+    d0 = (long long)kQScale - d1;
+    const double ms = (double)m2 * mscale;
+    const long long st = __double2ll_rn(ms);
+    s1 = __double2ll_rn(ms * (double)w);
+    s0 = st - s1;
+}
+
+// Moment sample (density weight and a second quantity m2) of the workgroup's species, in
+// fixed point, wave-aggregated like the charge.
+__device__ __forceinline__ void wave_moments(unsigned long long* M, int nn, int nc, float t, float m2, double mscale) {
+    unsigned long long* dens = M;
+    unsigned long long* sec = M + nn;
     const bool valid = t > 0.0f;
     int j = 0;
     float w = 0.0f;
-    if (valid) cell_of(t, nc, j, w);
+    long long d0 = 0, d1 = 0, s0 = 0, s1 = 0;
+    if (valid) {
+        cell_of(t, nc, j, w);
+        moment_parts(w, m2, mscale, d0, d1, s0, s1);
+    }
     const unsigned long long vm = __ballot(valid);
     if (vm == 0ull) return;
     const int lead = __builtin_ctzll(vm);
@@ -202,175 +227,98 @@ __device__ __forceinline__ void wave_moments(float* M, int nn, int nc, int s, fl
     const bool far = valid && (j < j0 - 1 || j > j0 + 2);
     if (__ballot(far) == 0ull) {
         const bool first = (int)(threadIdx.x & 63) == lead;
-        const float a = valid ? 1.0f - w : 0.0f, b = valid ? w : 0.0f;
 #pragma unroll
         for (int d = -1; d <= 3; ++d) {
             const int n = j0 + d;
-            const float c = (j == n ? a : 0.0f) + (j == n - 1 ? b : 0.0f);
-            const float cs = c * m2;
-            const float sd = __ockl_wfred_add_f32(c);
-            const float ss = __ockl_wfred_add_f32(cs);
-            if (first && sd != 0.0f) {
-                atomicAdd(&dens[n], sd);
-                atomicAdd(&sec[n], ss);
+            const int cd = (int)((j == n ? d0 : 0) + (j == n - 1 ? d1 : 0));   // <= 2^24
+            const long cs = (long)((j == n ? s0 : 0) + (j == n - 1 ? s1 : 0));
+            const int sd = __ockl_wfred_add_i32(cd);                           // <= 64 * 2^24
+            const long ss = __ockl_wfred_add_i64(cs);
+            if (first && sd != 0) {
+                atomicAdd(&dens[n], (unsigned long long)(long long)sd);
+                atomicAdd(&sec[n], (unsigned long long)(long long)ss);
             }
         }
     } else if (valid) {
-        lds_add2(dens, j, w, 1.0f);
-        lds_add2(sec, j, w, m2);
+        atomicAdd(&dens[j], (unsigned long long)d0);
+        atomicAdd(&dens[j + 1], (unsigned long long)d1);
+        atomicAdd(&sec[j], (unsigned long long)s0);
+        atomicAdd(&sec[j + 1], (unsigned long long)s1);
     }
 }
 
-__device__ __forceinline__ void sample_moments(const Params& P, const Lds& L, int s, float x, float vx,
-                                               float v2) {
+// Moment sample of an ionisation product (rare): the electron goes to the workgroup's LDS
+// sums (products arise in electron workgroups), the ion straight to the global sums.
+__device__ __forceinline__ void sample_product(const Params& P, const Lds& L, int s, float x, float m2) {
     const int nn = P.n_cells + 1;
     int j;
     float w;
     cell_of(x, P.n_cells, j, w);
     if (s == 0) {
-        lds_add2(L.M, j, w, 1.0f);
-        lds_add2(L.M + 2 * nn, j, w, P.half_m_over_e[0] * v2);
+        long long d0, d1, s0, s1;
+        moment_parts(w, m2, P.mscale[0], d0, d1, s0, s1);
+        atomicAdd(&L.M[j], (unsigned long long)d0);
+        atomicAdd(&L.M[j + 1], (unsigned long long)d1);
+        atomicAdd(&L.M[nn + j], (unsigned long long)s0);
+        atomicAdd(&L.M[nn + j + 1], (unsigned long long)s1);
     } else {
-        lds_add2(L.M + nn, j, w, 1.0f);
-        lds_add2(L.M + 3 * nn, j, w, vx);
+        unsafeAtomicAdd(&P.mom[nn + j], (double)(1.0f - w));
+        unsafeAtomicAdd(&P.mom[nn + j + 1], (double)w);
+        unsafeAtomicAdd(&P.mom[3 * nn + j], (double)(m2 - m2 * w));
+        unsafeAtomicAdd(&P.mom[3 * nn + j + 1], (double)(m2 * w));
     }
 }
 
-// One particle of species S in slot i, whose x, vx (and id; and, for electrons on completing
-// launches, vy, vz) were loaded by the caller.
-// On return, tq is the position to deposit as charge (<= 0: none) and tm, m2 the position
-// and second quantity of the moment sample (tm <= 0: none); the caller deposits both
-// wave-aggregated.
-template <int MODE, int S>
-__device__ __forceinline__ void particle(const Params& P, const Lds& L, int64_t i, float x, float vx, uint32_t pid,
-                                         float vy, float vz, uint32_t stepf, unsigned cur, int64_t ns0,
-                                         int64_t ns1, bool sample, float& tq, float& tm, float& m2) {
-    tq = -1.0f;
-    tm = -1.0f;
-    m2 = 0.0f;
-    if (!(x > 0.0f)) {   // hole (or a corrupted coordinate)
-        if (x != x) atomicOr(&L.cnt[kCntErr], kErrNumeric);
-        if ((MODE & kComplete) && P.dec[S]) P.dec[S][i] = 0;
-        return;
-    }
-    if (MODE == kDeposit) {
-        tq = x;
-        return;
-    }
-    int j;
-    float w;
-    cell_of(x, P.n_cells, j, w);
-    const float E = fmaf(w, L.E[j + 1] - L.E[j], L.E[j]);   // cloud-in-cell gather
-    const float kE = P.kick[S] * E;                          // half kick, Sec. 2.5 Verlet
-    bool dirty = false;
-
-    if (MODE & kComplete) {
-        vx += kE;   // v^n
-        const uint4 A = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kCollision, P.key0, P.key1);
-        int8_t code = 0;
-        if ((A.x >> 8) < P.T[S]) {   // null-collision candidate (integer test)
-            code = 1;
-            if (S == 1) {            // ions read vy, vz only when they are candidates
-                vy = P.vy[cur][1][i];
-                vz = P.vz[cur][1][i];
-            }
-            float vtx = 0.0f, vty = 0.0f, vtz = 0.0f;
-            if (S == 1) {   // gas atom from the Maxwellian at T_gas
-                const uint4 B = philox(pid, 0u, stepf, (1u << 8) | kTarget, P.key0, P.key1);
-                float z0, z1, z2, z3;
-                normal2(B.x, B.y, z0, z1);
-                normal2(B.z, B.w, z2, z3);
-                vtx = P.vT * z0;
-                vty = P.vT * z1;
-                vtz = P.vT * z2;
-            }
-            const float gx = vx - vtx, gy = vy - vty, gz = vz - vtz;
-            const float g2 = gx * gx + gy * gy + gz * gz;
-            const float gm = sqrtf(g2);
-            const float R = u01(A.y) * P.numax[S];
-            float c = 0.0f;
-            int sel = -1;
-            for (int q = 0; q < P.nproc; ++q) {
-                const ProcDev& p = P.proc[q];
-                if (p.species != S) continue;
-                c = fmaf(nsigma(p, P.tab, p.efac * g2), gm, c);
-                if (sel < 0 && R < c) sel = q;
-            }
-            if (c > P.numax[S]) atomicAdd(&L.cnt[kCntViol + S], 1u);
-            if (sel >= 0) {
-                code = (int8_t)(2 + sel);
-                atomicAdd(&L.cnt[kCntColl + sel], 1u);
-                const ProcDev& p = P.proc[sel];
-                const uint4 Cw = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kScatter, P.key0, P.key1);
-                float n1x, n1y, n1z;
-                iso_dir(Cw.x, Cw.y, n1x, n1y, n1z);
-                dirty = true;
-                if (p.kind == 0 || p.kind == 3) {   // elastic / isotropic: CM-isotropic two-body
-                    const float fa = P.fa[S], fb = P.fb[S];
-                    const float sgb = fb * gm;
-                    vx = fmaf(sgb, n1x, fmaf(fa, vx, fb * vtx));
-                    vy = fmaf(sgb, n1y, fmaf(fa, vy, fb * vty));
-                    vz = fmaf(sgb, n1z, fmaf(fa, vz, fb * vtz));
-                } else if (S == 0 && p.kind == 1) {   // excitation: lose the threshold energy
-                    const float eps = P.half_m_over_e[0] * g2;
-                    const float sp = sqrtf(fmaxf(eps - p.thr, 0.0f) * P.two_e_over_m_e);
-                    vx = sp * n1x;
-                    vy = sp * n1y;
-                    vz = sp * n1z;
-                } else if (S == 0 && p.kind == 2) {   // ionisation: equal share of eps - eps_iz
-                    const float eps = P.half_m_over_e[0] * g2;
-                    const float sp = sqrtf(fmaxf(eps - p.thr, 0.0f) * P.e_over_m_e);
-                    vx = sp * n1x;
-                    vy = sp * n1y;
-                    vz = sp * n1z;
-                    float n2x, n2y, n2z;
-                    iso_dir(Cw.z, Cw.w, n2x, n2y, n2z);
-                    const uint4 D = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kNewIon, P.key0, P.key1);
-                    float y0, y1, y2, y3;
-                    normal2(D.x, D.y, y0, y1);
-                    normal2(D.z, D.w, y2, y3);
-                    const unsigned k = atomicAdd(&P.ctrl->n_births, 1u);
-                    if ((int)k < P.max_births && ns0 + (int64_t)k < P.cap[0] && ns1 + (int64_t)k < P.cap[1]) {
-                        P.birth_parent[k] = pid;
-                        // products at the parent's position x^n with end-of-step velocities
-                        float cev[3] = {sp * n2x, sp * n2y, sp * n2z};
-                        float civ[3] = {P.vT * y0, P.vT * y1, P.vT * y2};
-                        if (sample) {
-                            sample_moments(P, L, 0, x, cev[0],
-                                           cev[0] * cev[0] + cev[1] * cev[1] + cev[2] * cev[2]);
-                            sample_moments(P, L, 1, x, civ[0], 0.0f);
-                        }
-                        float cex = x, cix = x;
-                        if (MODE & kAdvance) {   // products are moved from the next step on
-                            cev[0] += P.kick[0] * E;
-                            civ[0] += P.kick[1] * E;
-                            cex = absorb_or_deposit(P, L, 0, fmaf(cev[0], P.dt_over_dx, x));
-                            cix = absorb_or_deposit(P, L, 1, fmaf(civ[0], P.dt_over_dx, x));
-                        }
-                        const int64_t se = ns0 + k, si = ns1 + k;
-                        P.x[cur][0][se] = cex;
-                        P.vx[cur][0][se] = cev[0];
-                        P.vy[cur][0][se] = cev[1];
-                        P.vz[cur][0][se] = cev[2];
-                        P.x[cur][1][si] = cix;
-                        P.vx[cur][1][si] = civ[0];
-                        P.vy[cur][1][si] = civ[1];
-                        P.vz[cur][1][si] = civ[2];
-                        if (P.dec[0]) P.dec[0][se] = 0;
-                        if (P.dec[1]) P.dec[1][si] = 0;
-                    }
-                } else {   // backward: the ion leaves with the atom's velocity
-                    vx = vtx;
-                    vy = vty;
-                    vz = vtz;
-                }
-            }
-        }
-        if (P.dec[S]) P.dec[S][i] = code;
+// Products of one ionisation at the parent's position x^n.
+template <int MODE>
+__device__ __forceinline__ void spawn_products(const Params& P, const Lds& L, float x, float E, float sp, float n2x,
+                                            float n2y, float n2z, uint4 D, uint32_t pid, unsigned cur, int64_t ns0,
+                                            int64_t ns1, bool sample) {
+    float y0, y1, y2, y3;
+    normal2(D.x, D.y, y0, y1);
+    normal2(D.z, D.w, y2, y3);
+    const unsigned k = atomicAdd(&P.ctrl->n_births, 1u);
+    if ((int)k < P.max_births && ns0 + (int64_t)k < P.cap[0] && ns1 + (int64_t)k < P.cap[1]) {
+        st_agent(&P.birth_parent[k], pid);
+        // products at the parent's position x^n with end-of-step velocities
+        float cev[3] = {sp * n2x, sp * n2y, sp * n2z};
+        float civ[3] = {P.vT * y0, P.vT * y1, P.vT * y2};
         if (sample) {
-            tm = x;
-            m2 = S == 0 ? P.half_m_over_e[0] * (vx * vx + vy * vy + vz * vz) : vx;
+            sample_product(P, L, 0, x, P.half_m_over_e[0] * (cev[0] * cev[0] + cev[1] * cev[1] + cev[2] * cev[2]));
+            sample_product(P, L, 1, x, civ[0]);
         }
+        float cex = x, cix = x;
+        if (MODE & kAdvance) {   // products are moved from the next step on
+            cev[0] += P.kick[0] * E;
+            civ[0] += P.kick[1] * E;
+            cex = absorb_or_deposit(P, L, 0, fmaf(cev[0], P.dt_over_dx, x));
+            cix = absorb_or_deposit(P, L, 1, fmaf(civ[0], P.dt_over_dx, x));
+        }
+        const int64_t se = ns0 + k, si = ns1 + k;
+        P.x[cur][0][se] = cex;
+        P.vx[cur][0][se] = cev[0];
+        P.vy[cur][0][se] = cev[1];
+        P.vz[cur][0][se] = cev[2];
+        P.x[cur][1][si] = cix;
+        P.vx[cur][1][si] = civ[0];
+        P.vy[cur][1][si] = civ[1];
+        P.vz[cur][1][si] = civ[2];
+        if (P.dec[0]) P.dec[0][se] = 0;
+        if (P.dec[1]) P.dec[1][si] = 0;
+    }
+}
+
+// Finish a particle whose collision test (if any) is done: moment sample of the end-of-step
+// state, first half kick and drift of the next step, absorption, stores.  On return tq is
+// the position to deposit as charge (<= 0: none) and tm, m2 the position and second
+// quantity of the moment sample (tm <= 0: none); the caller deposits both wave-aggregated.
+template <int MODE, int S>
+__device__ __forceinline__ void finish(const Params& P, const Lds& L, int64_t i, float x, float vx, float vy,
+                                       float vz, bool dirty, float kE, bool sample, unsigned cur, float& tq,
+                                       float& tm, float& m2) {
+    if ((MODE & kComplete) && sample) {
+        tm = x;
+        m2 = S == 0 ? P.half_m_over_e[0] * (vx * vx + vy * vy + vz * vz) : vx;
     }
     if (MODE & kAdvance) {
         vx += kE;                                  // v^{n+1/2}
@@ -385,41 +333,248 @@ __device__ __forceinline__ void particle(const Params& P, const Lds& L, int64_t 
     }
 }
 
-// Particles [begin, end) of species S, kBatch per thread with all their loads issued first.
-constexpr int kBatch = 4;
+// Streaming part for one particle of species S in slot i (x, vx, id and, for electrons on
+// completing launches, vy, vz loaded by the caller): gather E^n once, complete the previous
+// step's kick, and test for a collision candidate with one integer comparison.
+// Non-candidates are finished here; a candidate returns true with its completed v_x in vx and
+// the second Philox word in rword, to be queued.
+template <int MODE, int S>
+__device__ __forceinline__ bool stream_particle(const Params& P, const Lds& L, int64_t i, float x, float& vx,
+                                                uint32_t pid, float vy, float vz, uint32_t stepf, unsigned cur,
+                                                bool sample, float& tq, float& tm, float& m2, uint32_t& rword) {
+    if (!(x > 0.0f)) {   // hole (or a corrupted coordinate)
+        if (x != x) atomicOr(&L.cnt[kCntErr], kErrNumeric);
+        if ((MODE & kComplete) && P.dec[S]) P.dec[S][i] = 0;
+        return false;
+    }
+    if (MODE == kDeposit) {
+        tq = x;
+        return false;
+    }
+    int j;
+    float w;
+    cell_of(x, P.n_cells, j, w);
+    const float E = fmaf(w, L.E[j + 1] - L.E[j], L.E[j]);   // cloud-in-cell gather
+    const float kE = P.kick[S] * E;                          // half kick, Sec. 2.5 Verlet
+    if (MODE & kComplete) {
+        vx += kE;   // v^n
+        const uint4 A = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kCollision, P.key0, P.key1);
+        if ((A.x >> 8) < P.T[S]) {   // null-collision candidate
+            rword = A.y;
+            return true;
+        }
+        if (P.dec[S]) P.dec[S][i] = 0;
+    }
+    finish<MODE, S>(P, L, i, x, vx, vy, vz, false, kE, sample, cur, tq, tm, m2);
+    return false;
+}
 
+// Null-collision MCC of one queued candidate (Sec. 2.5), then finish it.
+template <int MODE, int S>
+__device__ __forceinline__ void collide_entry(const Params& P, const Lds& L, int64_t i, float x, float vx,
+                                              float vy, float vz, uint32_t pid, uint32_t rword, uint32_t stepf,
+                                              unsigned cur, int64_t ns0, int64_t ns1, bool sample, float& tq,
+                                              float& tm, float& m2) {
+    int j;
+    float w;
+    cell_of(x, P.n_cells, j, w);
+    const float E = fmaf(w, L.E[j + 1] - L.E[j], L.E[j]);
+    const float kE = P.kick[S] * E;
+    if (S == 1) {   // ions read vy, vz only when they are candidates
+        vy = P.vy[cur][1][i];
+        vz = P.vz[cur][1][i];
+    }
+    int8_t code = 1;
+    bool dirty = false;
+    float vtx = 0.0f, vty = 0.0f, vtz = 0.0f;
+    if (S == 1) {   // gas atom from the Maxwellian at T_gas
+        const uint4 B = philox(pid, 0u, stepf, (1u << 8) | kTarget, P.key0, P.key1);
+        float z0, z1, z2, z3;
+        normal2(B.x, B.y, z0, z1);
+        normal2(B.z, B.w, z2, z3);
+        vtx = P.vT * z0;
+        vty = P.vT * z1;
+        vtz = P.vT * z2;
+    }
+    const float gx = vx - vtx, gy = vy - vty, gz = vz - vtz;
+    const float g2 = gx * gx + gy * gy + gz * gz;
+    const float gm = sqrtf(g2);
+    const float R = u01(rword) * P.numax[S];
+    // n_gas sigma_j [1/m] of the species' processes, four at a time with all their
+    // table loads issued before any is used: zero below the threshold, energy raised
+    // to the floor emin, the last point at or beyond the table end, linear
+    // interpolation in between; selection in config order
+    float c = 0.0f;
+    int sel = -1;
+    const int nsp = P.sp_n[S];
+#pragma unroll 1
+    for (int k0 = 0; k0 < nsp; k0 += 4) {
+        float ta[4], tb[4], tf[4];
+        bool tbelow[4], ttop[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k0 + k < nsp) {
+                const ProcDev& p = P.proc[P.sp_idx[S][k0 + k]];
+                const float eps = p.efac * g2;
+                const float t = fmaxf(eps, p.emin) * p.inv_de;
+                tbelow[k] = eps < p.thr;
+                ttop[k] = t >= (float)(p.n - 1);
+                const int kk = ttop[k] ? p.n - 2 : (int)t;
+                tf[k] = t - (float)kk;
+                ta[k] = P.tab[p.off + kk];
+                tb[k] = P.tab[p.off + kk + 1];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k0 + k < nsp) {
+                const float sig = tbelow[k] ? 0.0f : (ttop[k] ? tb[k] : fmaf(tb[k] - ta[k], tf[k], ta[k]));
+                c = fmaf(sig, gm, c);
+                if (sel < 0 && R < c) sel = P.sp_idx[S][k0 + k];
+            }
+        }
+    }
+    if (c > P.numax[S]) atomicAdd(&L.cnt[kCntViol + S], 1u);
+    if (sel >= 0) {
+        code = (int8_t)(2 + sel);
+        atomicAdd(&L.cnt[kCntColl + sel], 1u);
+        const ProcDev& p = P.proc[sel];
+        const uint4 Cw = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kScatter, P.key0, P.key1);
+        float n1x, n1y, n1z;
+        iso_dir(Cw.x, Cw.y, n1x, n1y, n1z);
+        dirty = true;
+        if (p.kind == 0 || p.kind == 3) {   // elastic / isotropic: CM-isotropic two-body
+            const float fa = P.fa[S], fb = P.fb[S];
+            const float sgb = fb * gm;
+            vx = fmaf(sgb, n1x, fmaf(fa, vx, fb * vtx));
+            vy = fmaf(sgb, n1y, fmaf(fa, vy, fb * vty));
+            vz = fmaf(sgb, n1z, fmaf(fa, vz, fb * vtz));
+        } else if (S == 0 && p.kind == 1) {   // excitation: lose the threshold energy
+            const float eps = P.half_m_over_e[0] * g2;
+            const float sp = sqrtf(fmaxf(eps - p.thr, 0.0f) * P.two_e_over_m_e);
+            vx = sp * n1x;
+            vy = sp * n1y;
+            vz = sp * n1z;
+        } else if (S == 0 && p.kind == 2) {   // ionisation: equal share of eps - eps_iz
+            const float eps = P.half_m_over_e[0] * g2;
+            const float sp = sqrtf(fmaxf(eps - p.thr, 0.0f) * P.e_over_m_e);
+            vx = sp * n1x;
+            vy = sp * n1y;
+            vz = sp * n1z;
+            float n2x, n2y, n2z;
+            iso_dir(Cw.z, Cw.w, n2x, n2y, n2z);
+            const uint4 D = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kNewIon, P.key0, P.key1);
+            spawn_products<MODE>(P, L, x, E, sp, n2x, n2y, n2z, D, pid, cur, ns0, ns1, sample);
+        } else {   // backward: the ion leaves with the atom's velocity
+            vx = vtx;
+            vy = vty;
+            vz = vtz;
+        }
+    }
+    if (P.dec[S]) P.dec[S][i] = code;
+    finish<MODE, S>(P, L, i, x, vx, vy, vz, dirty, kE, sample, cur, tq, tm, m2);
+}
+
+// Process the top `count` queued candidates, one per thread, then pop them.
+template <int MODE, int S>
+__device__ __forceinline__ void drain_queue(const Params& P, const Lds& L, unsigned count, uint32_t stepf,
+                                            unsigned cur, int64_t ns0, int64_t ns1, bool sample) {
+    const unsigned tid = threadIdx.x;
+    const unsigned n = L.cnt[kCntQueue];
+    float tq = -1.0f, tm = -1.0f, m2 = 0.0f;
+    if (tid < count) {
+        const unsigned e = n - count + tid;
+        collide_entry<MODE, S>(P, L, (int64_t)L.qslot[e], L.qx[e], L.qvx[e], L.qvy[e], L.qvz[e], L.qid[e],
+                               L.qr[e], stepf, cur, ns0, ns1, sample, tq, tm, m2);
+    }
+    wave_charge(L.Q, P.n_cells, tq, S ? 1 : -1);
+    if (sample) wave_moments(L.M, P.n_cells + 1, P.n_cells, tm, m2, P.mscale[S]);
+    __syncthreads();
+    if (tid == 0) L.cnt[kCntQueue] = n - count;
+    __syncthreads();
+}
+
+// Particles [begin, end) of species S, one per thread per iteration, with the next
+// iteration's loads issued before the current particle is processed (one copy of the
+// particle code per species keeps the kernel within the instruction cache).  Collision
+// candidates are compacted into the LDS queue and processed at least half a workgroup at a
+// time, so the long MCC path runs on dense waves instead of on a few lanes of every wave.
 template <int MODE, int S>
 __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t begin, int64_t end, uint32_t stepf,
                                           unsigned cur, int64_t ns0, int64_t ns1, bool sample) {
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63;
     const float* __restrict__ X = P.x[cur][S];
     const float* __restrict__ VX = P.vx[cur][S];
     const uint32_t* __restrict__ ID = P.id[cur][S];
     const float* __restrict__ VY = P.vy[cur][S];
     const float* __restrict__ VZ = P.vz[cur][S];
     constexpr bool kPreloadYZ = (MODE & kComplete) && S == 0;
-    for (int64_t base = begin; base < end; base += (int64_t)nt * kBatch) {
-        float x[kBatch], vx[kBatch], vy[kBatch], vz[kBatch];
-        uint32_t id[kBatch];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int64_t i = base + (int64_t)u * nt + tid;
-            const bool in = i < end;
-            x[u] = in ? X[i] : -1.0f;
-            vx[u] = (MODE != kDeposit && in) ? VX[i] : 0.0f;
-            id[u] = ((MODE & kComplete) && in) ? ID[i] : 0u;
-            vy[u] = (kPreloadYZ && in) ? VY[i] : 0.0f;
-            vz[u] = (kPreloadYZ && in) ? VZ[i] : 0.0f;
+    int64_t i = begin + tid;
+    float x = -1.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
+    uint32_t id = 0u;
+    if (i < end) {
+        x = X[i];
+        if (MODE != kDeposit) vx = VX[i];
+        if (MODE & kComplete) id = ID[i];
+        if (kPreloadYZ) {
+            vy = VY[i];
+            vz = VZ[i];
         }
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int64_t i = base + (int64_t)u * nt + tid;
-            float tq = -1.0f, tm = -1.0f, m2 = 0.0f;
-            if (i < end)
-                particle<MODE, S>(P, L, i, x[u], vx[u], id[u], vy[u], vz[u], stepf, cur, ns0, ns1, sample, tq, tm, m2);
-            wave_charge(L.Q, P.n_cells, tq, S ? 1 : -1);
-            if (sample) wave_moments(L.M, P.n_cells + 1, P.n_cells, S, tm, m2);
+    }
+    for (int64_t base = begin; base < end; base += nt) {
+        const int64_t inext = i + nt;
+        float xn = -1.0f, vxn = 0.0f, vyn = 0.0f, vzn = 0.0f;
+        uint32_t idn = 0u;
+        if (inext < end) {
+            xn = X[inext];
+            if (MODE != kDeposit) vxn = VX[inext];
+            if (MODE & kComplete) idn = ID[inext];
+            if (kPreloadYZ) {
+                vyn = VY[inext];
+                vzn = VZ[inext];
+            }
         }
+        float tq = -1.0f, tm = -1.0f, m2 = 0.0f;
+        uint32_t rw = 0u;
+        bool cand = false;
+        if (i < end) cand = stream_particle<MODE, S>(P, L, i, x, vx, id, vy, vz, stepf, cur, sample, tq, tm, m2, rw);
+        wave_charge(L.Q, P.n_cells, tq, S ? 1 : -1);
+        if (sample) wave_moments(L.M, P.n_cells + 1, P.n_cells, tm, m2, P.mscale[S]);
+        if (MODE & kComplete) {
+            const unsigned long long qm = __ballot(cand);
+            if (qm) {
+                const int first = __builtin_ctzll(qm);
+                unsigned qb = 0;
+                if (lane == first) qb = atomicAdd(&L.cnt[kCntQueue], (unsigned)__popcll(qm));
+                qb = __shfl(qb, first, 64);
+                if (cand) {
+                    const unsigned e = qb + (unsigned)__popcll(qm & ((1ull << lane) - 1ull));
+                    L.qslot[e] = (uint32_t)i;
+                    L.qid[e] = id;
+                    L.qr[e] = rw;
+                    L.qx[e] = x;
+                    L.qvx[e] = vx;
+                    L.qvy[e] = vy;
+                    L.qvz[e] = vz;
+                }
+            }
+            __syncthreads();
+            const unsigned waiting = L.cnt[kCntQueue];
+            if (waiting > (unsigned)(nt / 2))
+                drain_queue<MODE, S>(P, L, min(waiting, (unsigned)nt), stepf, cur, ns0, ns1, sample);
+        }
+        i = inext;
+        x = xn;
+        vx = vxn;
+        vy = vyn;
+        vz = vzn;
+        id = idn;
+    }
+    if (MODE & kComplete) {
+        __syncthreads();
+        const unsigned left = L.cnt[kCntQueue];
+        if (left > 0) drain_queue<MODE, S>(P, L, left, stepf, cur, ns0, ns1, sample);
     }
 }
 
@@ -463,46 +618,33 @@ __device__ double block_incl_scan(double* a, int n, double* scratch) {
     return total;
 }
 
-// Poisson with phi_0 = phi0, phi_N = 0 (Sec. 2, 2.2; central differences, Sec. 2.3):
-// D_i = phi_{i+1} - phi_i obeys D_i = D_0 - (dx/eps0) sum_{k=1..i} Q_k, and
-// sum_i D_i = -phi0 fixes D_0; phi follows from a second prefix sum.  Boundary fields by
-// Gauss's law over the half cells next to the electrodes.
-__device__ void solve_field(const Params& P, double* sd, double phi0, double& E0, double& EN) {
+// Poisson with phi_0 = phi0, phi_N = 0 (Sec. 2, 2.2; central differences, Sec. 2.3), on
+// node charges Qd [C/m^2] already in LDS.  D_i = phi_{i+1} - phi_i obeys
+// D_i = D_0 - (dx/eps0) sum_{k=1..i} Q_k, and sum_i D_i = -phi0 fixes D_0; phi follows from
+// a second prefix sum.  Boundary fields by Gauss's law over the half cells next to the
+// electrodes.  Writes phi (FP64) and E (FP32) to global memory; returns E_0 and E_N.
+__device__ void solve_field(const Params& P, const double* Qd, double* work, double* phis, double* scratch,
+                            double phi0, double& E0, double& EN) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int nc = P.n_cells, nn = nc + 1;
-    double* work = sd;            // nn
-    double* phis = sd + nn;       // nn
-    double* scratch = sd + 2 * nn;   // 16 + 2
     const double dxe = P.dx_d / P.eps0;
-    for (int i = tid; i < nn; i += nt) {
-        const double q = (double)(long long)ld_agent(&P.Qi[i]) * (kQScaleInv * P.e0W);
-        P.Q_last[i] = q;
-        P.Qi[i] = 0ull;
-        work[i] = (i >= 1 && i < nc) ? q : 0.0;
-        if (i == 0) scratch[16] = q;
-        if (i == nc) scratch[17] = q;
-    }
+    for (int i = tid; i < nc; i += nt) work[i] = (i >= 1) ? Qd[i] : 0.0;
     __syncthreads();
-    const double Q0 = scratch[16], QN = scratch[17];
-    const double S = [&] {
-        block_incl_scan(work, nc, scratch);   // work[i] = sum_{k=1..i} Q_k, i < nc
-        // sum_{i<nc} work[i]
-        double s = 0.0;
-        for (int i = tid; i < nc; i += nt) s += work[i];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if ((tid & 63) == 0) scratch[tid >> 6] = s;
-        __syncthreads();
-        double tot = 0.0;
-        for (int w = 0; w < (nt >> 6); ++w) tot += scratch[w];
-        __syncthreads();
-        return tot;
-    }();
+    block_incl_scan(work, nc, scratch);   // work[i] = sum_{k=1..i} Q_k, i < nc
+    double sp = 0.0;
+    for (int i = tid; i < nc; i += nt) sp += work[i];
+    for (int off = 32; off > 0; off >>= 1) sp += __shfl_xor(sp, off, 64);
+    if ((tid & 63) == 0) scratch[tid >> 6] = sp;
+    __syncthreads();
+    double S = 0.0;
+    for (int w = 0; w < (nt >> 6); ++w) S += scratch[w];
+    __syncthreads();
     const double D0 = (dxe * S - phi0) / (double)nc;
     for (int i = tid; i < nc; i += nt) work[i] = D0 - dxe * work[i];
     __syncthreads();
     block_incl_scan(work, nc, scratch);   // work[i] = sum_{k<=i} D_k
     for (int i = tid; i < nn; i += nt) {
-        double ph = (i == 0) ? phi0 : (i == nc ? 0.0 : phi0 + work[i - 1]);
+        const double ph = (i == 0) ? phi0 : (i == nc ? 0.0 : phi0 + work[i - 1]);
         phis[i] = ph;
         P.phi[i] = ph;
     }
@@ -511,9 +653,9 @@ __device__ void solve_field(const Params& P, double* sd, double phi0, double& E0
     for (int i = tid; i < nn; i += nt) {
         double e;
         if (i == 0)
-            e = (phis[0] - phis[1]) * invdx - Q0 / P.eps0;
+            e = (phis[0] - phis[1]) * invdx - Qd[0] / P.eps0;
         else if (i == nc)
-            e = (phis[nc - 1] - phis[nc]) * invdx + QN / P.eps0;
+            e = (phis[nc - 1] - phis[nc]) * invdx + Qd[nc] / P.eps0;
         else
             e = (phis[i - 1] - phis[i + 1]) * inv2dx;
         P.E[i] = (float)e;
@@ -528,12 +670,11 @@ __device__ void solve_field(const Params& P, double* sd, double phi0, double& E0
 
 // Ids of this launch's ionisation products: the k-th parent in ascending id order gives
 // next_id_e + k and next_id_i + k.
-__device__ void assign_birth_ids(const Params& P, unsigned char* smem, unsigned cur, int64_t ns0,
-                                 int64_t ns1, unsigned nbv, int64_t nid0, int64_t nid1) {
+__device__ void assign_birth_ids(const Params& P, uint32_t* keys, unsigned cur, int64_t ns0, int64_t ns1,
+                                 unsigned nbv, int64_t nid0, int64_t nid1) {
     const int tid = threadIdx.x, nt = blockDim.x;
     if (nbv == 0) return;
     if (nbv <= (unsigned)kBirthSortCap) {
-        uint32_t* keys = reinterpret_cast<uint32_t*>(smem);
         unsigned n2 = 1;
         while (n2 < nbv) n2 <<= 1;
         for (unsigned k = tid; k < n2; k += nt) keys[k] = k < nbv ? ld_agent(&P.birth_parent[k]) : 0xFFFFFFFFu;
@@ -577,87 +718,139 @@ __device__ void assign_birth_ids(const Params& P, unsigned char* smem, unsigned 
     }
 }
 
-// Work of the last workgroup of a launch.
+// LDS layout of the epilogue (bytes): control block copy, then FP64 node arrays.
+constexpr int kEpiCtrlBytes = 512;
+static_assert(sizeof(Ctrl) <= kEpiCtrlBytes && sizeof(Ctrl) % 8 == 0, "control block copy");
+constexpr int kEpiNodesPerThread = 8;   // the host keeps n_cells + 1 <= 8 * blockDim
+
+// Work of the last workgroup of a launch.  Every global value it needs is loaded in one
+// round trip (control block, charge grid, the previous potential and its window sum), the
+// bookkeeping and the Poisson solve run in LDS, and all results are stored at the end.
 template <int MODE>
 __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, unsigned cur, int64_t ns0,
                          int64_t ns1, bool sample) {
     Ctrl* C = P.ctrl;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int nn = P.n_cells + 1;
-    double* sd = reinterpret_cast<double*>(smem);
+    const int nc = P.n_cells, nn = nc + 1;
+    Ctrl* cs = reinterpret_cast<Ctrl*>(smem);
+    double* Qd = reinterpret_cast<double*>(smem + kEpiCtrlBytes);
+    double* work = Qd + nn;
+    double* phis = work + nn;
+    double* scratch = phis + nn;                                  // 32 doubles
+    uint32_t* keys = reinterpret_cast<uint32_t*>(scratch + 32);   // kBirthSortCap
+    constexpr bool kSolve = (MODE & (kAdvance | kDeposit)) != 0;
+    constexpr int kWords = (int)(sizeof(Ctrl) / 8);
+    __syncthreads();   // the particle pass is done with LDS
+
+    // ---- one round trip of loads
+    unsigned long long* cw = reinterpret_cast<unsigned long long*>(cs);
+    unsigned long long* gw = reinterpret_cast<unsigned long long*>(C);
+    for (int w = tid; w < kWords; w += nt) cw[w] = ld_agent(&gw[w]);
+    double phi_old[kEpiNodesPerThread], mom_old[kEpiNodesPerThread];
+    const bool do_phi_sample = (MODE & kComplete) && sample;
+    if (do_phi_sample) {
+#pragma unroll
+        for (int r = 0; r < kEpiNodesPerThread; ++r) {
+            const int i = tid + r * nt;
+            phi_old[r] = i < nn ? P.phi[i] : 0.0;
+            mom_old[r] = i < nn ? P.mom[4 * nn + i] : 0.0;
+        }
+    }
+    if (kSolve) {
+        long long q[kEpiNodesPerThread];
+#pragma unroll
+        for (int r = 0; r < kEpiNodesPerThread; ++r) {
+            const int i = tid + r * nt;
+            q[r] = i < nn ? (long long)ld_agent(&P.Qi[i]) : 0ll;
+        }
+        const double scale = kQScaleInv * P.e0W;
+#pragma unroll
+        for (int r = 0; r < kEpiNodesPerThread; ++r) {
+            const int i = tid + r * nt;
+            if (i < nn) Qd[i] = (double)q[r] * scale;
+        }
+    }
     __syncthreads();
+
+    // ---- completion of the previous step: births, phi sample
     if (MODE & kComplete) {
-        const unsigned nb = ld_agent(&C->n_births);
+        const unsigned nb = cs->n_births;
         unsigned nbv = nb;
         if ((int64_t)nbv > P.max_births) nbv = (unsigned)P.max_births;
         if ((int64_t)nbv > P.cap[0] - ns0) nbv = (unsigned)(P.cap[0] - ns0);
         if ((int64_t)nbv > P.cap[1] - ns1) nbv = (unsigned)(P.cap[1] - ns1);
-        const int64_t nid0 = C->next_id[0], nid1 = C->next_id[1];
-        assign_birth_ids(P, smem, cur, ns0, ns1, nbv, nid0, nid1);
-        if (sample)
-            for (int i = tid; i < nn; i += nt) P.mom[4 * nn + i] += P.phi[i];   // phi^n
+        const int64_t nid0 = cs->next_id[0], nid1 = cs->next_id[1];
+        assign_birth_ids(P, keys, cur, ns0, ns1, nbv, nid0, nid1);
         if (tid == 0) {
-            if (nb > nbv) C->err |= (nbv == (unsigned)P.max_births) ? kErrBirths : kErrCapacity;
-            if (nid0 + nbv > 0x100000000ll || nid1 + nbv > 0x100000000ll) C->err |= kErrIds;
-            C->n_slots[0] = ns0 + nbv;
-            C->n_slots[1] = ns1 + nbv;
-            C->next_id[0] = nid0 + nbv;
-            C->next_id[1] = nid1 + nbv;
-            C->n_alive[0] += nbv;
-            C->n_alive[1] += nbv;
-            C->births_total += nbv;
-            C->births_lost += nb - nbv;
-            C->n_births = 0;
-            if (sample) C->n_samples += 1;
+            if (nb > nbv) cs->err |= (nbv == (unsigned)P.max_births) ? kErrBirths : kErrCapacity;
+            if (nid0 + nbv > 0x100000000ll || nid1 + nbv > 0x100000000ll) cs->err |= kErrIds;
+            cs->n_slots[0] = ns0 + nbv;
+            cs->n_slots[1] = ns1 + nbv;
+            cs->next_id[0] = nid0 + nbv;
+            cs->next_id[1] = nid1 + nbv;
+            cs->n_alive[0] += nbv;
+            cs->n_alive[1] += nbv;
+            cs->births_total += nbv;
+            cs->births_lost += nb - nbv;
+            cs->n_births = 0;
+            if (sample) cs->n_samples += 1;
+        }
+        if (do_phi_sample) {
+#pragma unroll
+            for (int r = 0; r < kEpiNodesPerThread; ++r) {
+                const int i = tid + r * nt;
+                if (i < nn) P.mom[4 * nn + i] = mom_old[r] + phi_old[r];   // phi^n
+            }
         }
         __syncthreads();
     }
-    if (MODE & kAdvance) {
+
+    // ---- the field for the new time level
+    if (kSolve) {
         double E0, EN;
-        const double t1 = (double)(step + 1) * P.dt_d;
-        solve_field(P, sd, P.V0 * sin(P.omega * t1), E0, EN);
+        const double t1 = (double)(step + ((MODE & kAdvance) ? 1 : 0)) * P.dt_d;
+        solve_field(P, Qd, work, phis, scratch, P.V0 * sin(P.omega * t1), E0, EN);
+        for (int i = tid; i < nn; i += nt) {
+            P.Q_last[i] = Qd[i];
+            P.Qi[i] = 0ull;
+        }
         if (tid == 0) {
-            unsigned long long a[2][2];
-            for (int s = 0; s < 2; ++s)
-                for (int e = 0; e < 2; ++e) {
-                    a[s][e] = ld_agent(&C->absorbed_step[s][e]);
-                    C->absorbed_step[s][e] = 0;
-                    C->absorbed_total[s][e] += a[s][e];
-                    C->absorbed_window[s][e] += a[s][e];
+            if (MODE & kAdvance) {
+                unsigned long long a[2][2];
+                for (int s = 0; s < 2; ++s)
+                    for (int e = 0; e < 2; ++e) {
+                        a[s][e] = cs->absorbed_step[s][e];
+                        cs->absorbed_step[s][e] = 0;
+                        cs->absorbed_total[s][e] += a[s][e];
+                        cs->absorbed_window[s][e] += a[s][e];
+                    }
+                cs->particle_steps += cs->n_alive[0] + cs->n_alive[1];
+                cs->n_alive[0] -= (int64_t)(a[0][0] + a[0][1]);
+                cs->n_alive[1] -= (int64_t)(a[1][0] + a[1][1]);
+                const double J = P.eps0 * (E0 - cs->E0_prev) / P.dt_d +
+                                 P.e0W * ((double)a[0][0] - (double)a[1][0]) / P.dt_d;
+                cs->J_last = J;
+                const int64_t n1 = step + 1;
+                cs->J_period_max = fmax(cs->J_period_max, fabs(J));
+                if (n1 % P.steps_per_period == 0) {
+                    if (cs->period_valid) {
+                        cs->J_max_sum += cs->J_period_max;
+                        cs->n_periods += 1;
+                    }
+                    cs->J_period_max = 0.0;
+                    cs->period_valid = 1;
                 }
-            C->particle_steps += C->n_alive[0] + C->n_alive[1];
-            C->n_alive[0] -= (int64_t)(a[0][0] + a[0][1]);
-            C->n_alive[1] -= (int64_t)(a[1][0] + a[1][1]);
-            const double J = P.eps0 * (E0 - C->E0_prev) / P.dt_d +
-                             P.e0W * ((double)a[0][0] - (double)a[1][0]) / P.dt_d;
-            C->J_last = J;
-            C->E0_prev = E0;
-            C->sigma0 = P.eps0 * E0;
-            C->sigmad = -P.eps0 * EN;
-            const int64_t n1 = step + 1;
-            C->J_period_max = fmax(C->J_period_max, fabs(J));
-            if (n1 % P.steps_per_period == 0) {
-                if (C->period_valid) {
-                    C->J_max_sum += C->J_period_max;
-                    C->n_periods += 1;
-                }
-                C->J_period_max = 0.0;
-                C->period_valid = 1;
+                cs->n_steps_window += 1;
+                cs->step = n1;
             }
-            C->n_steps_window += 1;
-            C->step = n1;
+            cs->E0_prev = E0;
+            cs->sigma0 = P.eps0 * E0;
+            cs->sigmad = -P.eps0 * EN;
         }
     }
-    if (MODE == kDeposit) {
-        double E0, EN;
-        solve_field(P, sd, P.V0 * sin(P.omega * (double)step * P.dt_d), E0, EN);
-        if (tid == 0) {
-            C->E0_prev = E0;
-            C->sigma0 = P.eps0 * E0;
-            C->sigmad = -P.eps0 * EN;
-        }
-    }
-    if (tid == 0) C->done = 0;
+    if (tid == 0) cs->done = 0;
+    __syncthreads();
+    for (int w = tid; w < kWords; w += nt) gw[w] = cw[w];
 }
 
 template <int MODE>
@@ -669,8 +862,16 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     Lds L;
     L.cnt = reinterpret_cast<uint32_t*>(smem);
     L.Q = reinterpret_cast<unsigned long long*>(smem + kCntSlots * 4);
-    L.E = reinterpret_cast<float*>(L.Q + nn);
-    L.M = L.E + nn;
+    L.M = L.Q + nn;
+    L.E = reinterpret_cast<float*>(L.M + 2 * nn);
+    const int qcap = nt + nt / 2;
+    L.qslot = reinterpret_cast<uint32_t*>(L.E + nn);
+    L.qid = L.qslot + qcap;
+    L.qr = L.qid + qcap;
+    L.qx = reinterpret_cast<float*>(L.qr + qcap);
+    L.qvx = L.qx + qcap;
+    L.qvy = L.qvx + qcap;
+    L.qvz = L.qvy + qcap;
 
     const int64_t step = C->step;
     const unsigned cur = C->cur;
@@ -683,12 +884,9 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
         L.E[i] = (MODE == kDeposit) ? 0.0f : P.E[i];
         L.Q[i] = 0ull;
     }
-    if (sample)
-        for (int i = tid; i < 4 * nn; i += nt) L.M[i] = 0.0f;
-    __syncthreads();
 
     // Workgroups are species-pure: the first G_e take the electrons, the rest the ions, in
-    // proportion to the slot counts (a single workgroup takes both).
+    // proportion to the slot counts (a single workgroup takes both, one after the other).
     const int G = gridDim.x;
     int64_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
     if (G == 1) {
@@ -712,19 +910,34 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
             e1 = min(b1 + per, ns1);
         }
     }
-    if (e0 > b0) run_range<MODE, 0>(P, L, b0, e0, stepf, cur, ns0, ns1, sample);
-    if (e1 > b1) run_range<MODE, 1>(P, L, b1, e1, stepf, cur, ns0, ns1, sample);
+    for (int s = 0; s < 2; ++s) {
+        const int64_t b = s ? b1 : b0, e = s ? e1 : e0;
+        if (!(e > b)) continue;
+        if (sample)
+            for (int i = tid; i < 2 * nn; i += nt) L.M[i] = 0ull;
+        __syncthreads();
+        if (s == 0)
+            run_range<MODE, 0>(P, L, b, e, stepf, cur, ns0, ns1, sample);
+        else
+            run_range<MODE, 1>(P, L, b, e, stepf, cur, ns0, ns1, sample);
+        __syncthreads();
+        if (sample) {   // this species' moment sums: density weight, then energy (e) or v_x (i)
+            double* dens = P.mom + (s ? nn : 0);
+            double* sec = P.mom + (s ? 3 * nn : 2 * nn);
+            const double inv2 = 1.0 / P.mscale[s];
+            for (int i = tid; i < nn; i += nt) {
+                const long long m0 = (long long)L.M[i], m1 = (long long)L.M[nn + i];
+                if (m0 != 0) unsafeAtomicAdd(&dens[i], (double)m0 * kQScaleInv);
+                if (m1 != 0) unsafeAtomicAdd(&sec[i], (double)m1 * inv2);
+            }
+        }
+    }
     __syncthreads();
 
     for (int i = tid; i < nn; i += nt) {
         const unsigned long long q = L.Q[i];
         if (q != 0ull) atomicAdd(&P.Qi[i], q);
     }
-    if (sample)
-        for (int i = tid; i < 4 * nn; i += nt) {
-            const float m = L.M[i];
-            if (m != 0.0f) unsafeAtomicAdd(&P.mom[i], (double)m);
-        }
     if (tid < 4) {
         if (L.cnt[kCntAbs + tid]) atomicAdd(&C->absorbed_step[tid >> 1][tid & 1], (unsigned long long)L.cnt[kCntAbs + tid]);
     } else if (tid < 4 + kMaxProc) {
@@ -734,7 +947,7 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     } else if (tid == kCntErr) {
         if (L.cnt[tid]) atomicOr(&C->err, L.cnt[tid]);
     }
-    __threadfence();
+    wait_memory_complete();
     __syncthreads();
     if (tid == 0) {
         const unsigned prev = atomicAdd(&C->done, 1u);
@@ -742,7 +955,6 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     }
     __syncthreads();
     if (!L.cnt[kCntLast]) return;
-    __threadfence();
     epilogue<MODE>(P, smem, step, cur, ns0, ns1, sample);
 }
 
@@ -876,7 +1088,7 @@ __global__ void __launch_bounds__(1024) sort_scatter_kernel(Params P, unsigned* 
             P.id[nxt][s][pos] = P.id[cur][s][i];
         }
     }
-    __threadfence();
+    wait_memory_complete();
     __syncthreads();
     if (tid == 0) {
         const unsigned prev = atomicAdd(&C->done, 1u);
@@ -884,7 +1096,6 @@ __global__ void __launch_bounds__(1024) sort_scatter_kernel(Params P, unsigned* 
     }
     __syncthreads();
     if (!flag[0] || tid != 0) return;
-    __threadfence();
     C->n_slots[0] = (int64_t)ld_agent(&C->sort_alive[0]);
     C->n_slots[1] = (int64_t)ld_agent(&C->sort_alive[1]);
     C->cur = nxt;

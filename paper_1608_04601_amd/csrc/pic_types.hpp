@@ -10,6 +10,7 @@
 namespace pic {
 
 constexpr int kMaxProc = 16;
+constexpr int kMaxProcPerSpecies = 8;
 constexpr int kMaxCells = 4096;
 constexpr int kBirthSortCap = 2048;   // births per step ranked in LDS; more take a slow path
 // Charge deposit in fixed point: a particle's two cloud-in-cell weights are integers
@@ -17,6 +18,12 @@ constexpr int kBirthSortCap = 2048;   // births per step ranked in LDS; more tak
 // independent of the order of accumulation (bitwise reproducible runs).
 constexpr float kQScale = 16777216.0f;
 constexpr double kQScaleInv = 1.0 / 16777216.0;
+// Per-step moment sums in LDS are integer fixed point too (LDS integer atomics are far
+// faster than floating-point ones): density weights in units of 2^-24 particle, the second
+// quantity in units of 1/mscale (electron energy: 2^-16 eV; ion v_x: 2^-8 m/s).  Each
+// workgroup converts its sums to FP64 when it adds them to the window sums.
+constexpr double kMomScaleE = 65536.0;
+constexpr double kMomScaleI = 256.0;
 
 // particle-pass modes (bit set)
 constexpr int kComplete = 1;   // finish the previous step: second half kick, MCC, births, moments
@@ -86,10 +93,13 @@ struct Params {
     double* Q_last;      // charge of the last solve [C/m^2] [nn]
     double* phi;         // node potential [V] [nn]
     double* mom;         // moment window sums [5][nn]: dens_e, dens_i, energy_e, flux_i, phi
+    double mscale[2];    // fixed-point scale of the second moment quantity per species
     uint32_t* birth_parent;   // [max_births]
     int8_t* dec[2];      // decision record per slot, or null
     const float* tab;    // n_gas * sigma tables [1/m]
     ProcDev proc[kMaxProc];
+    int32_t sp_n[2];                          // processes per species
+    int32_t sp_idx[2][kMaxProcPerSpecies];    // their table indices, in config order
     int32_t nproc;
     int32_t n_cells;
     int32_t max_births;
