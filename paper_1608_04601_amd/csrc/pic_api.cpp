@@ -155,6 +155,51 @@ double compute_numax(const pic_handle* h, int s) {
     return h->n_gas * best;
 }
 
+// Electron null-collision pre-test (Sec. 2.5): for bins uniform in g^2 up to the end of
+// the longest electron table, an upper bound of n_gas sum_j sigma_j g as the kernel
+// evaluates it from the FP32 tables.  On a bin, each process's interpolated cross section
+// is at most the largest table value between the points that bracket the bin's energies
+// (both ends widened by 0.1 %), and g at most the root of the widened upper end; the sum
+// is raised by another 0.1 %, which covers the FP32 rounding of the kernel's evaluation.
+// A candidate with R nu_max at or above its bin's bound therefore selects no process.
+// Entries beyond the last bin, and for a species without electron processes, are +inf.
+std::vector<float> null_bounds(const pic_handle* h, const std::vector<float>& htab, const pic::Params& P,
+                               float* inv_gbin) {
+    const int nb = pic::kNullBins;
+    std::vector<float> U(nb + 1, std::numeric_limits<float>::infinity());
+    *inv_gbin = 0.0f;
+    const int ne = P.sp_n[0];
+    if (ne == 0) return U;
+    double g2_top = 0.0;
+    for (int k = 0; k < ne; ++k) {
+        const pic::ProcDev& d = P.proc[P.sp_idx[0][k]];
+        const double de = 1.0 / (double)d.inv_de;
+        g2_top = std::max(g2_top, (d.n - 1) * de / (double)d.efac);
+    }
+    if (!(g2_top > 0.0) || !std::isfinite(g2_top)) return U;
+    const double width = g2_top / nb;
+    *inv_gbin = (float)(1.0 / width);
+    for (int b = 0; b < nb; ++b) {
+        const double lo = b * width * (1.0 - 1e-3), hi = (b + 1) * width * (1.0 + 1e-3);
+        double sum = 0.0;
+        for (int k = 0; k < ne; ++k) {
+            const pic::ProcDev& d = P.proc[P.sp_idx[0][k]];
+            const double tlo = std::max((double)d.efac * lo, (double)d.emin) * (double)d.inv_de;
+            const double thi = std::max((double)d.efac * hi, (double)d.emin) * (double)d.inv_de;
+            const int k0 = std::min(std::max((int)std::floor(tlo), 0), d.n - 1);
+            const int k1 = std::min((int)std::ceil(thi) + 1, d.n - 1);
+            double mx = 0.0;
+            for (int q = k0; q <= k1; ++q) mx = std::max(mx, (double)htab[(size_t)d.off + q]);
+            sum += mx;
+        }
+        const double bound = sum * std::sqrt(hi) * (1.0 + 1e-3);
+        float f = (float)bound;
+        if ((double)f < bound) f = std::nextafter(f, std::numeric_limits<float>::infinity());
+        U[b] = f;
+    }
+    return U;
+}
+
 std::string validate(const pic_config* c) {
     auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
     auto nonneg = [](double v) { return std::isfinite(v) && v >= 0.0; };
@@ -348,12 +393,15 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         size_t ntab = 0;
         for (const pic_xsec& p : h->xs) ntab += (size_t)p.n_points;
         float* tab = nullptr;
-        if (!dev_alloc(h, &P.ctrl, 1) || !dev_alloc(h, &P.E, nn) || !dev_alloc(h, &P.Qi, nn) ||
+        float* nullbound = nullptr;
+        if (!dev_alloc(h, &P.ctrl, 1) || !dev_alloc(h, &P.E, nn) || !dev_alloc(h, &P.Qs, (size_t)2 * nn) ||
+            !dev_alloc(h, &P.Qdep, (size_t)2 * nn) || !dev_alloc(h, &nullbound, (size_t)pic::kNullBins + 1) ||
             !dev_alloc(h, &P.Q_last, nn) || !dev_alloc(h, &P.phi, nn) || !dev_alloc(h, &P.mom, (size_t)5 * nn) ||
             !dev_alloc(h, &P.birth_parent, (size_t)c.max_births_per_step) || !dev_alloc(h, &tab, std::max<size_t>(ntab, 1)) ||
             !dev_alloc(h, &h->sort_cnt, (size_t)2 * nc) || !dev_alloc(h, &h->sort_cursor, (size_t)2 * nc))
             goto fail_init;
         P.tab = tab;
+        P.nullbound = nullbound;
         std::vector<float> htab;
         htab.reserve(ntab);
         P.nproc = (int)h->xs.size();
@@ -377,6 +425,7 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
             d.efac = (float)(0.5 * m_frame / kE0);
             for (double v : h->tables[j]) htab.push_back((float)(h->n_gas * v));
         }
+        const std::vector<float> hbound = null_bounds(h, htab, P, &P.inv_gbin);
         P.n_cells = nc;
         P.max_births = c.max_births_per_step;
         P.moments_every = c.moments_every;
@@ -408,11 +457,13 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         P.mscale[1] = pic::kMomScaleI;
 
         // launch shape: one workgroup per contiguous particle range; LDS holds the node
-        // field, the private charge grid and the four moment grids
+        // field, the private deposit and moment grids, the null-collision bounds and the
+        // candidate queue
         h->threads = nn <= 1025 ? 256 : 1024;
-        // counters, fixed-point charge, two fixed-point moment sums, field, candidate queue
-        // (1.5 x threads entries of seven words)
-        const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 16 + 4) + (size_t)(h->threads + h->threads / 2) * 7 * 4;
+        // counters, fixed-point deposit, fixed-point moment sum, field, bounds, candidate
+        // queue (1.5 x threads entries of seven words)
+        const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 8 + 4) + (size_t)(pic::kNullBins + 1) * 4 +
+                                (size_t)(h->threads + h->threads / 2) * 7 * 4;
         // last workgroup: control block copy, three FP64 node arrays, scratch, birth keys
         const size_t epi_lds = 512 + (size_t)24 * nn + 256 + (size_t)pic::kBirthSortCap * 4;
         h->lds = std::max(pass_lds, epi_lds);
@@ -428,7 +479,10 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         if (!hip_ok(h, pic::set_pass_lds_limit(h->lds), "hipFuncSetAttribute")) goto fail_init;
 
         if (!hip_ok(h, hipMemcpyAsync(tab, htab.data(), htab.size() * sizeof(float), hipMemcpyHostToDevice, h->stream),
-                    "upload tables"))
+                    "upload tables") ||
+            !hip_ok(h, hipMemcpyAsync(nullbound, hbound.data(), hbound.size() * sizeof(float), hipMemcpyHostToDevice,
+                                      h->stream),
+                    "upload null-collision bounds"))
             goto fail_init;
         pic::Ctrl c0{};
         for (int s = 0; s < 2; ++s) {
@@ -438,7 +492,8 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         }
         c0.period_valid = 1;
         if (!hip_ok(h, hipMemcpyAsync(P.ctrl, &c0, sizeof(c0), hipMemcpyHostToDevice, h->stream), "upload ctrl") ||
-            !hip_ok(h, hipMemsetAsync(P.Qi, 0, nn * sizeof(unsigned long long), h->stream), "zero Q") ||
+            !hip_ok(h, hipMemsetAsync(P.Qs, 0, 2 * nn * sizeof(unsigned long long), h->stream), "zero Q") ||
+            !hip_ok(h, hipMemsetAsync(P.Qdep, 0, 2 * nn * sizeof(double), h->stream), "zero deposit") ||
             !hip_ok(h, hipMemsetAsync(P.mom, 0, 5 * nn * sizeof(double), h->stream), "zero moments") ||
             !hip_ok(h, hipMemsetAsync(h->sort_cnt, 0, 2 * nc * sizeof(unsigned), h->stream), "zero sort counts"))
             goto fail_init;
@@ -652,7 +707,7 @@ int pic_set_particles(pic_handle* h, int species, const double* x, const float* 
     c.next_id[species] = next_id == 0 ? 0 : (int64_t)next_id;
     c.step = step;
     if (!hip_ok(h, hipMemcpy(h->P.ctrl, &c, sizeof(c), hipMemcpyHostToDevice), "write ctrl")) return h->status;
-    if (!hip_ok(h, hipMemset(h->P.Qi, 0, (h->cfg.n_cells + 1) * sizeof(unsigned long long)), "zero Q"))
+    if (!hip_ok(h, hipMemset(h->P.Qs, 0, 2 * (h->cfg.n_cells + 1) * sizeof(unsigned long long)), "zero Q"))
         return h->status;
     if (launch_pass_timed(h, pic::kDeposit)) return h->status;
     return check_device(h);

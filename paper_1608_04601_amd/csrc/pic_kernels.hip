@@ -79,12 +79,11 @@ __device__ __forceinline__ void cell_of(float t, int nc, int& j, float& w) {
     w = t - (float)j;
 }
 
-// Charge of one particle (sign q = +-1) to nodes j, j+1 in fixed point.
-__device__ __forceinline__ void lds_charge(unsigned long long* a, int j, float w, int q) {
-    const long long wq = (long long)__float2int_rn(w * kQScale);   // in [0, 2^24]
-    const long long total = (long long)kQScale;
-    atomicAdd(&a[j], (unsigned long long)(q * (total - wq)));
-    atomicAdd(&a[j + 1], (unsigned long long)(q * wq));
+// Deposit of one particle to nodes j, j+1 of its species' grid, in fixed point.
+__device__ __forceinline__ void lds_count(unsigned long long* a, int j, float w) {
+    const unsigned long long wq = (unsigned long long)__float2int_rn(w * kQScale);   // in [0, 2^24]
+    atomicAdd(&a[j], kQOne - wq);
+    atomicAdd(&a[j + 1], wq);
 }
 
 template <typename T>
@@ -112,14 +111,16 @@ __device__ __forceinline__ void wait_memory_complete() {
 enum : int { kCntAbs = 0, kCntColl = 4, kCntViol = 20, kCntErr = 22, kCntQueue = 23, kCntLast = 31, kCntSlots = 32 };
 
 // LDS of one workgroup of the particle pass.  A workgroup handles one species at a time:
-// M holds that species' two moment sums (density weight; electron energy or ion v_x).
-// Collision candidates wait in a queue (structure of arrays, 1.5 x blockDim entries) until
-// more than half a workgroup of them can be processed together.
+// Q holds that species' deposit and M its second moment quantity (electron energy or ion
+// v_x), U the electron null-collision bounds.  Collision candidates wait in a queue
+// (structure of arrays, 1.5 x blockDim entries) until more than half a workgroup of them
+// can be processed together.
 struct Lds {
     uint32_t* cnt;
-    unsigned long long* Q;   // fixed-point charge
+    unsigned long long* Q;   // fixed-point deposit
+    unsigned long long* M;   // fixed-point second moment quantity
     float* E;
-    unsigned long long* M;   // 2 x nn, fixed point
+    float* U;                // kNullBins + 1
     uint32_t* qslot;
     uint32_t* qid;
     uint32_t* qr;            // second Philox word of the collision draw
@@ -129,13 +130,22 @@ struct Lds {
     float* qvz;
 };
 
-// After the drift: absorb at the electrodes (Sec. 2.5, ties absorbed) or deposit.
+// After the drift of an ionisation product: absorb at the electrodes (Sec. 2.5, ties
+// absorbed) or deposit.  Products arise in electron workgroups: the electron goes to the
+// workgroup's grid, the ion straight to the global ion grid.
 __device__ __forceinline__ float absorb_or_deposit(const Params& P, const Lds& L, int s, float x) {
     if (x > 0.0f && x < P.ncf) {
         int j;
         float w;
         cell_of(x, P.n_cells, j, w);
-        lds_charge(L.Q, j, w, s ? 1 : -1);
+        if (s == 0) {
+            lds_count(L.Q, j, w);
+        } else {
+            const unsigned long long wq = (unsigned long long)__float2int_rn(w * kQScale);
+            unsigned long long* g = P.Qs + (P.n_cells + 1);
+            atomicAdd(&g[j], kQOne - wq);
+            atomicAdd(&g[j + 1], wq);
+        }
         return x;
     }
     if (x <= 0.0f)
@@ -148,7 +158,7 @@ __device__ __forceinline__ float absorb_or_deposit(const Params& P, const Lds& L
 }
 
 // After the drift, without depositing: returns x, or the hole marker after counting the
-// absorption (the caller deposits survivors wave-aggregated).
+// absorption (the caller deposits survivors).
 __device__ __forceinline__ float absorb_only(const Params& P, const Lds& L, int s, float x) {
     if (x > 0.0f && x < P.ncf) return x;
     if (x <= 0.0f)
@@ -160,113 +170,123 @@ __device__ __forceinline__ float absorb_only(const Params& P, const Lds& L, int 
     return -1.0f;
 }
 
-extern "C" __device__ int __ockl_wfred_add_i32(int);
-extern "C" __device__ long __ockl_wfred_add_i64(long);
+// Second moment quantity a = m2 * mscale of a sample at cell weight w, in fixed point: the
+// rounded total st and the right node's share s1.  Any physical sample has |a| < 2^30;
+// false for larger (or non-finite) values, which the caller adds to the FP64 sums directly.
+__device__ __forceinline__ bool moment_fixed(float a, float w, int& st, int& s1) {
+    if (!(fabsf(a) < 0x1p30f)) return false;
+    st = __float2int_rn(a);
+    s1 = __float2int_rn(a * w);
+    return true;
+}
 
-// Wave-aggregated cloud-in-cell deposits.  Called by every lane of a wave in converged
-// control flow; a lane with t <= 0 contributes nothing.  When the wave's cells lie within
-// four consecutive cells of the first contributing lane (cell-sorted particles), the
-// contributions to each of the five nodes they touch are summed across the wave with DPP
-// reductions and one lane adds them to LDS; otherwise every lane adds its own.  The charge
-// is integer (fixed point), so the result is the same either way.
-__device__ __forceinline__ void wave_charge(unsigned long long* Q, int nc, float t, int q) {
-    const bool valid = t > 0.0f;
-    int j = 0;
-    float w = 0.0f;
-    if (valid) cell_of(t, nc, j, w);
-    const unsigned long long vm = __ballot(valid);
-    if (vm == 0ull) return;
-    const int lead = __builtin_ctzll(vm);
-    const int j0 = __shfl(j, lead, 64);
-    const bool far = valid && (j < j0 - 1 || j > j0 + 2);
-    if (__ballot(far) == 0ull) {
-        const int wq = valid ? __float2int_rn(w * kQScale) : 0;
-        const int tot = valid ? (int)kQScale : 0;
-        const bool first = (int)(threadIdx.x & 63) == lead;
-#pragma unroll
-        for (int d = -1; d <= 3; ++d) {
-            const int n = j0 + d;
-            const int c = (j == n ? tot - wq : 0) + (j == n - 1 ? wq : 0);
-            const int sum = __ockl_wfred_add_i32(c);   // |sum| <= 64 * 2^24
-            if (first && sum != 0) atomicAdd(&Q[n], (unsigned long long)(long long)(q * sum));
-        }
-    } else if (valid) {
-        lds_charge(Q, j, w, q);
+__device__ __forceinline__ void moment_fp64(const Params& P, int s, int j, float w, float m2) {
+    double* sec = P.mom + (s ? 3 : 2) * (P.n_cells + 1);
+    unsafeAtomicAdd(&sec[j], (double)m2 * (1.0 - (double)w));
+    unsafeAtomicAdd(&sec[j + 1], (double)m2 * (double)w);
+}
+
+// One moment sample of species s added to LDS M at once (t <= 0: none).
+__device__ __forceinline__ void moment_direct(const Params& P, const Lds& L, int s, float t, float m2) {
+    if (!(t > 0.0f)) return;
+    int j;
+    float w;
+    cell_of(t, P.n_cells, j, w);
+    int st, s1;
+    if (moment_fixed(m2 * (float)P.mscale[s], w, st, s1)) {
+        atomicAdd(&L.M[j], (unsigned long long)(long long)(st - s1));
+        atomicAdd(&L.M[j + 1], (unsigned long long)(long long)s1);
+    } else {
+        moment_fp64(P, s, j, w, m2);
     }
 }
 
-// Fixed-point split of a moment sample at cell weight w: density weights (2^24 - d1, d1)
-// and second quantity (s0, s1) with s0 + s1 = round(m2 * mscale).
-__device__ __forceinline__ void moment_parts(float w, float m2, double mscale, long long& d0, long long& d1,
-                                             long long& s0, long long& s1) {
-    d1 = (long long)__float2int_rn(w * kQScale);
-    d0 = (long long)kQScale - d1;
-    const double ms = (double)m2 * mscale;
-    const long long st = __double2ll_rn(ms);
-    s1 = __double2ll_rn(ms * (double)w);
-    s0 = st - s1;
+// One deposit (t <= 0: none) added to LDS Q at once.
+__device__ __forceinline__ void deposit_direct(const Lds& L, int nc, float t) {
+    if (!(t > 0.0f)) return;
+    int j;
+    float w;
+    cell_of(t, nc, j, w);
+    lds_count(L.Q, j, w);
 }
 
-// Moment sample (density weight and a second quantity m2) of the workgroup's species, in
-// fixed point, wave-aggregated like the charge.
-__device__ __forceinline__ void wave_moments(unsigned long long* M, int nn, int nc, float t, float m2, double mscale) {
-    unsigned long long* dens = M;
-    unsigned long long* sec = M + nn;
-    const bool valid = t > 0.0f;
-    int j = 0;
-    float w = 0.0f;
-    long long d0 = 0, d1 = 0, s0 = 0, s1 = 0;
-    if (valid) {
-        cell_of(t, nc, j, w);
-        moment_parts(w, m2, mscale, d0, d1, s0, s1);
+// Per-lane run caches for cell-sorted particles (ions, which move a small fraction of a
+// cell per step): a lane's successive particles lie in the same cell most of the time, so
+// their contributions are summed in registers and reach LDS once per run.
+struct ChargeRun {
+    int c = -1;   // cell of the run
+    int n = 0;    // particles in it (at most 64, so d stays below 2^31)
+    int d = 0;    // sum of right-node weights
+};
+
+struct MomentRun {
+    int c = -1;
+    long long st = 0;   // sum of fixed-point totals
+    long long s1 = 0;   // sum of right-node shares
+};
+
+__device__ __forceinline__ void flush_run(const Lds& L, ChargeRun& r) {
+    if (r.n > 0) {
+        atomicAdd(&L.Q[r.c], (unsigned long long)(r.n * (int)kQOne - r.d));
+        atomicAdd(&L.Q[r.c + 1], (unsigned long long)r.d);
     }
-    const unsigned long long vm = __ballot(valid);
-    if (vm == 0ull) return;
-    const int lead = __builtin_ctzll(vm);
-    const int j0 = __shfl(j, lead, 64);
-    const bool far = valid && (j < j0 - 1 || j > j0 + 2);
-    if (__ballot(far) == 0ull) {
-        const bool first = (int)(threadIdx.x & 63) == lead;
-#pragma unroll
-        for (int d = -1; d <= 3; ++d) {
-            const int n = j0 + d;
-            const int cd = (int)((j == n ? d0 : 0) + (j == n - 1 ? d1 : 0));   // <= 2^24
-            const long cs = (long)((j == n ? s0 : 0) + (j == n - 1 ? s1 : 0));
-            const int sd = __ockl_wfred_add_i32(cd);                           // <= 64 * 2^24
-            const long ss = __ockl_wfred_add_i64(cs);
-            if (first && sd != 0) {
-                atomicAdd(&dens[n], (unsigned long long)(long long)sd);
-                atomicAdd(&sec[n], (unsigned long long)(long long)ss);
-            }
-        }
-    } else if (valid) {
-        atomicAdd(&dens[j], (unsigned long long)d0);
-        atomicAdd(&dens[j + 1], (unsigned long long)d1);
-        atomicAdd(&sec[j], (unsigned long long)s0);
-        atomicAdd(&sec[j + 1], (unsigned long long)s1);
-    }
+    r.n = 0;
+    r.d = 0;
 }
 
-// Moment sample of an ionisation product (rare): the electron goes to the workgroup's LDS
-// sums (products arise in electron workgroups), the ion straight to the global sums.
-__device__ __forceinline__ void sample_product(const Params& P, const Lds& L, int s, float x, float m2) {
+__device__ __forceinline__ void flush_run(const Lds& L, MomentRun& r) {
+    if (r.c >= 0) {
+        atomicAdd(&L.M[r.c], (unsigned long long)(r.st - r.s1));
+        atomicAdd(&L.M[r.c + 1], (unsigned long long)r.s1);
+    }
+    r.st = 0;
+    r.s1 = 0;
+}
+
+__device__ __forceinline__ void deposit_run(const Lds& L, int nc, ChargeRun& r, float t) {
+    if (!(t > 0.0f)) return;
+    int j;
+    float w;
+    cell_of(t, nc, j, w);
+    const int d1 = __float2int_rn(w * kQScale);
+    if (j != r.c || r.n == 64) {
+        flush_run(L, r);
+        r.c = j;
+    }
+    r.n += 1;
+    r.d += d1;
+}
+
+__device__ __forceinline__ void moment_run(const Params& P, const Lds& L, int s, MomentRun& r, float t, float m2) {
+    if (!(t > 0.0f)) return;
+    int j;
+    float w;
+    cell_of(t, P.n_cells, j, w);
+    int st, s1;
+    if (!moment_fixed(m2 * (float)P.mscale[s], w, st, s1)) {
+        moment_fp64(P, s, j, w, m2);
+        return;
+    }
+    if (j != r.c) {
+        flush_run(L, r);
+        r.c = j;
+    }
+    r.st += st;
+    r.s1 += s1;
+}
+
+// Moment sample of an ionisation product (rare), straight to the FP64 window sums: its
+// density weight (the density of all other particles comes from the deposit) and its
+// second quantity.
+__device__ __forceinline__ void sample_product(const Params& P, int s, float x, float m2) {
     const int nn = P.n_cells + 1;
     int j;
     float w;
     cell_of(x, P.n_cells, j, w);
-    if (s == 0) {
-        long long d0, d1, s0, s1;
-        moment_parts(w, m2, P.mscale[0], d0, d1, s0, s1);
-        atomicAdd(&L.M[j], (unsigned long long)d0);
-        atomicAdd(&L.M[j + 1], (unsigned long long)d1);
-        atomicAdd(&L.M[nn + j], (unsigned long long)s0);
-        atomicAdd(&L.M[nn + j + 1], (unsigned long long)s1);
-    } else {
-        unsafeAtomicAdd(&P.mom[nn + j], (double)(1.0f - w));
-        unsafeAtomicAdd(&P.mom[nn + j + 1], (double)w);
-        unsafeAtomicAdd(&P.mom[3 * nn + j], (double)(m2 - m2 * w));
-        unsafeAtomicAdd(&P.mom[3 * nn + j + 1], (double)(m2 * w));
-    }
+    double* dens = P.mom + s * nn;
+    unsafeAtomicAdd(&dens[j], 1.0 - (double)w);
+    unsafeAtomicAdd(&dens[j + 1], (double)w);
+    moment_fp64(P, s, j, w, m2);
 }
 
 // Products of one ionisation at the parent's position x^n.
@@ -284,8 +304,8 @@ __device__ __forceinline__ void spawn_products(const Params& P, const Lds& L, fl
         float cev[3] = {sp * n2x, sp * n2y, sp * n2z};
         float civ[3] = {P.vT * y0, P.vT * y1, P.vT * y2};
         if (sample) {
-            sample_product(P, L, 0, x, P.half_m_over_e[0] * (cev[0] * cev[0] + cev[1] * cev[1] + cev[2] * cev[2]));
-            sample_product(P, L, 1, x, civ[0]);
+            sample_product(P, 0, x, P.half_m_over_e[0] * (cev[0] * cev[0] + cev[1] * cev[1] + cev[2] * cev[2]));
+            sample_product(P, 1, x, civ[0]);
         }
         float cex = x, cix = x;
         if (MODE & kAdvance) {   // products are moved from the next step on
@@ -359,11 +379,25 @@ __device__ __forceinline__ bool stream_particle(const Params& P, const Lds& L, i
     if (MODE & kComplete) {
         vx += kE;   // v^n
         const uint4 A = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kCollision, P.key0, P.key1);
+        int8_t code = 0;
         if ((A.x >> 8) < P.T[S]) {   // null-collision candidate
-            rword = A.y;
-            return true;
+            // Electrons: R nu_max at or above the bound of the summed collision frequency
+            // over the particle's g^2 bin means no process can be selected, so the
+            // candidate is a null collision without the table lookups (the full test would
+            // find the same).
+            bool open = true;
+            if (S == 0) {
+                const float g2 = vx * vx + vy * vy + vz * vz;
+                const int b = (int)fminf(g2 * P.inv_gbin, (float)kNullBins);
+                open = !(u01(A.y) * P.numax[0] >= L.U[b]);
+            }
+            if (open) {
+                rword = A.y;
+                return true;
+            }
+            code = 1;
         }
-        if (P.dec[S]) P.dec[S][i] = 0;
+        if (P.dec[S]) P.dec[S][i] = code;
     }
     finish<MODE, S>(P, L, i, x, vx, vy, vz, false, kE, sample, cur, tq, tm, m2);
     return false;
@@ -487,8 +521,8 @@ __device__ __forceinline__ void drain_queue(const Params& P, const Lds& L, unsig
         collide_entry<MODE, S>(P, L, (int64_t)L.qslot[e], L.qx[e], L.qvx[e], L.qvy[e], L.qvz[e], L.qid[e],
                                L.qr[e], stepf, cur, ns0, ns1, sample, tq, tm, m2);
     }
-    wave_charge(L.Q, P.n_cells, tq, S ? 1 : -1);
-    if (sample) wave_moments(L.M, P.n_cells + 1, P.n_cells, tm, m2, P.mscale[S]);
+    deposit_direct(L, P.n_cells, tq);
+    if (sample) moment_direct(P, L, S, tm, m2);
     __syncthreads();
     if (tid == 0) L.cnt[kCntQueue] = n - count;
     __syncthreads();
@@ -513,6 +547,8 @@ __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t
     int64_t i = begin + tid;
     float x = -1.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
     uint32_t id = 0u;
+    ChargeRun qrun;
+    MomentRun mrun;
     if (i < end) {
         x = X[i];
         if (MODE != kDeposit) vx = VX[i];
@@ -539,8 +575,13 @@ __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t
         uint32_t rw = 0u;
         bool cand = false;
         if (i < end) cand = stream_particle<MODE, S>(P, L, i, x, vx, id, vy, vz, stepf, cur, sample, tq, tm, m2, rw);
-        wave_charge(L.Q, P.n_cells, tq, S ? 1 : -1);
-        if (sample) wave_moments(L.M, P.n_cells + 1, P.n_cells, tm, m2, P.mscale[S]);
+        if (S == 0) {   // electrons leave cell order within a step or two
+            deposit_direct(L, P.n_cells, tq);
+            if (sample) moment_direct(P, L, S, tm, m2);
+        } else {
+            deposit_run(L, P.n_cells, qrun, tq);
+            if (sample) moment_run(P, L, S, mrun, tm, m2);
+        }
         if (MODE & kComplete) {
             const unsigned long long qm = __ballot(cand);
             if (qm) {
@@ -570,6 +611,10 @@ __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t
         vy = vyn;
         vz = vzn;
         id = idn;
+    }
+    if (S == 1) {
+        flush_run(L, qrun);
+        if (sample) flush_run(L, mrun);
     }
     if (MODE & kComplete) {
         __syncthreads();
@@ -757,17 +802,24 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
         }
     }
     if (kSolve) {
-        long long q[kEpiNodesPerThread];
+        // this launch's deposit per species: net node charge to Qd, particle counts to
+        // work (electrons) and phis (ions) until they are stored as the next density sample
+        unsigned long long q0[kEpiNodesPerThread], q1[kEpiNodesPerThread];
 #pragma unroll
         for (int r = 0; r < kEpiNodesPerThread; ++r) {
             const int i = tid + r * nt;
-            q[r] = i < nn ? (long long)ld_agent(&P.Qi[i]) : 0ll;
+            q0[r] = i < nn ? ld_agent(&P.Qs[i]) : 0ull;
+            q1[r] = i < nn ? ld_agent(&P.Qs[nn + i]) : 0ull;
         }
         const double scale = kQScaleInv * P.e0W;
 #pragma unroll
         for (int r = 0; r < kEpiNodesPerThread; ++r) {
             const int i = tid + r * nt;
-            if (i < nn) Qd[i] = (double)q[r] * scale;
+            if (i < nn) {
+                Qd[i] = (double)((long long)q1[r] - (long long)q0[r]) * scale;
+                work[i] = (double)q0[r] * kQScaleInv;
+                phis[i] = (double)q1[r] * kQScaleInv;
+            }
         }
     }
     __syncthreads();
@@ -799,7 +851,13 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
 #pragma unroll
             for (int r = 0; r < kEpiNodesPerThread; ++r) {
                 const int i = tid + r * nt;
-                if (i < nn) P.mom[4 * nn + i] = mom_old[r] + phi_old[r];   // phi^n
+                if (i < nn) {
+                    P.mom[4 * nn + i] = mom_old[r] + phi_old[r];   // phi^n
+                    // densities at x^n: the deposit that produced x^n (the products of
+                    // this launch were added by their parents' workgroups)
+                    unsafeAtomicAdd(&P.mom[i], P.Qdep[i]);
+                    unsafeAtomicAdd(&P.mom[nn + i], P.Qdep[nn + i]);
+                }
             }
         }
         __syncthreads();
@@ -807,13 +865,20 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
 
     // ---- the field for the new time level
     if (kSolve) {
+        for (int r = 0; r < kEpiNodesPerThread; ++r) {
+            const int i = tid + r * nt;
+            if (i < nn) {
+                P.Qdep[i] = work[i];
+                P.Qdep[nn + i] = phis[i];
+                P.Qs[i] = 0ull;
+                P.Qs[nn + i] = 0ull;
+            }
+        }
+        __syncthreads();
         double E0, EN;
         const double t1 = (double)(step + ((MODE & kAdvance) ? 1 : 0)) * P.dt_d;
         solve_field(P, Qd, work, phis, scratch, P.V0 * sin(P.omega * t1), E0, EN);
-        for (int i = tid; i < nn; i += nt) {
-            P.Q_last[i] = Qd[i];
-            P.Qi[i] = 0ull;
-        }
+        for (int i = tid; i < nn; i += nt) P.Q_last[i] = Qd[i];
         if (tid == 0) {
             if (MODE & kAdvance) {
                 unsigned long long a[2][2];
@@ -863,9 +928,10 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     L.cnt = reinterpret_cast<uint32_t*>(smem);
     L.Q = reinterpret_cast<unsigned long long*>(smem + kCntSlots * 4);
     L.M = L.Q + nn;
-    L.E = reinterpret_cast<float*>(L.M + 2 * nn);
+    L.E = reinterpret_cast<float*>(L.M + nn);
+    L.U = L.E + nn;
     const int qcap = nt + nt / 2;
-    L.qslot = reinterpret_cast<uint32_t*>(L.E + nn);
+    L.qslot = reinterpret_cast<uint32_t*>(L.U + kNullBins + 1);
     L.qid = L.qslot + qcap;
     L.qr = L.qid + qcap;
     L.qx = reinterpret_cast<float*>(L.qr + qcap);
@@ -880,10 +946,10 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     const uint32_t stepf = (uint32_t)step;
 
     for (int i = tid; i < kCntSlots; i += nt) L.cnt[i] = 0;
-    for (int i = tid; i < nn; i += nt) {
-        L.E[i] = (MODE == kDeposit) ? 0.0f : P.E[i];
-        L.Q[i] = 0ull;
-    }
+    if (MODE != kDeposit)
+        for (int i = tid; i < nn; i += nt) L.E[i] = P.E[i];
+    if (MODE & kComplete)
+        for (int i = tid; i <= kNullBins; i += nt) L.U[i] = P.nullbound[i];
 
     // Workgroups are species-pure: the first G_e take the electrons, the rest the ions, in
     // proportion to the slot counts (a single workgroup takes both, one after the other).
@@ -913,30 +979,29 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     for (int s = 0; s < 2; ++s) {
         const int64_t b = s ? b1 : b0, e = s ? e1 : e0;
         if (!(e > b)) continue;
-        if (sample)
-            for (int i = tid; i < 2 * nn; i += nt) L.M[i] = 0ull;
+        for (int i = tid; i < nn; i += nt) {
+            L.Q[i] = 0ull;
+            if (sample) L.M[i] = 0ull;
+        }
         __syncthreads();
         if (s == 0)
             run_range<MODE, 0>(P, L, b, e, stepf, cur, ns0, ns1, sample);
         else
             run_range<MODE, 1>(P, L, b, e, stepf, cur, ns0, ns1, sample);
         __syncthreads();
-        if (sample) {   // this species' moment sums: density weight, then energy (e) or v_x (i)
-            double* dens = P.mom + (s ? nn : 0);
-            double* sec = P.mom + (s ? 3 * nn : 2 * nn);
-            const double inv2 = 1.0 / P.mscale[s];
-            for (int i = tid; i < nn; i += nt) {
-                const long long m0 = (long long)L.M[i], m1 = (long long)L.M[nn + i];
-                if (m0 != 0) unsafeAtomicAdd(&dens[i], (double)m0 * kQScaleInv);
+        // this species' deposit, and its energy (e) or v_x (i) sums
+        unsigned long long* qg = P.Qs + s * nn;
+        double* sec = P.mom + (s ? 3 * nn : 2 * nn);
+        const double inv2 = 1.0 / P.mscale[s];
+        for (int i = tid; i < nn; i += nt) {
+            const unsigned long long q = L.Q[i];
+            if (q != 0ull) atomicAdd(&qg[i], q);
+            if (sample) {
+                const long long m1 = (long long)L.M[i];
                 if (m1 != 0) unsafeAtomicAdd(&sec[i], (double)m1 * inv2);
             }
         }
-    }
-    __syncthreads();
-
-    for (int i = tid; i < nn; i += nt) {
-        const unsigned long long q = L.Q[i];
-        if (q != 0ull) atomicAdd(&P.Qi[i], q);
+        __syncthreads();
     }
     if (tid < 4) {
         if (L.cnt[kCntAbs + tid]) atomicAdd(&C->absorbed_step[tid >> 1][tid & 1], (unsigned long long)L.cnt[kCntAbs + tid]);

@@ -18,12 +18,17 @@ constexpr int kBirthSortCap = 2048;   // births per step ranked in LDS; more tak
 // independent of the order of accumulation (bitwise reproducible runs).
 constexpr float kQScale = 16777216.0f;
 constexpr double kQScaleInv = 1.0 / 16777216.0;
-// Per-step moment sums in LDS are integer fixed point too (LDS integer atomics are far
-// faster than floating-point ones): density weights in units of 2^-24 particle, the second
-// quantity in units of 1/mscale (electron energy: 2^-16 eV; ion v_x: 2^-8 m/s).  Each
-// workgroup converts its sums to FP64 when it adds them to the window sums.
+constexpr unsigned long long kQOne = 16777216ull;
+// The density moment of a sampled step is the deposit of the positions it samples (the
+// previous launch's charge deposit, kept per species).  The second moment quantity is
+// summed in LDS in integer fixed point (LDS integer atomics are far faster than
+// floating-point ones), in units of 1/mscale: electron energy 2^-16 eV, ion v_x 2^-8 m/s.
+// Each workgroup converts its sums to FP64 when it adds them to the window sums.
 constexpr double kMomScaleE = 65536.0;
 constexpr double kMomScaleI = 256.0;
+// Null-collision pre-test for electrons: bins uniform in g^2 up to the end of the tables,
+// each with an upper bound of the summed collision frequency over the bin.
+constexpr int kNullBins = 256;
 
 // particle-pass modes (bit set)
 constexpr int kComplete = 1;   // finish the previous step: second half kick, MCC, births, moments
@@ -89,7 +94,8 @@ struct Params {
     int64_t cap[2];
     Ctrl* ctrl;
     float* E;            // node field, FP32 copy for the gather [nn]
-    unsigned long long* Qi;  // node charge accumulator, signed fixed point: 2^24 per particle [nn]
+    unsigned long long* Qs;  // node deposit per species, fixed point: 2^24 per particle [2][nn]
+    double* Qdep;        // the last launch's deposit per species [particles] [2][nn]
     double* Q_last;      // charge of the last solve [C/m^2] [nn]
     double* phi;         // node potential [V] [nn]
     double* mom;         // moment window sums [5][nn]: dens_e, dens_i, energy_e, flux_i, phi
@@ -97,6 +103,9 @@ struct Params {
     uint32_t* birth_parent;   // [max_births]
     int8_t* dec[2];      // decision record per slot, or null
     const float* tab;    // n_gas * sigma tables [1/m]
+    const float* nullbound;   // [kNullBins + 1] electron collision-frequency bounds [1/s]
+    float inv_gbin;           // bins per unit g^2 [s^2/m^2]
+    float pad1;
     ProcDev proc[kMaxProc];
     int32_t sp_n[2];                          // processes per species
     int32_t sp_idx[2][kMaxProcPerSpecies];    // their table indices, in config order
