@@ -461,9 +461,9 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         // candidate queue
         h->threads = nn <= 1025 ? 256 : 1024;
         // counters, fixed-point deposit, fixed-point moment sum, field, bounds, candidate
-        // queue (1.5 x threads entries of seven words)
+        // queues (128 entries of three words per wave)
         const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 8 + 4) + (size_t)(pic::kNullBins + 1) * 4 +
-                                (size_t)(h->threads + h->threads / 2) * 7 * 4;
+                                (size_t)(h->threads / 64) * 128 * 3 * 4;
         // last workgroup: control block copy, three FP64 node arrays, scratch, birth keys
         const size_t epi_lds = 512 + (size_t)24 * nn + 256 + (size_t)pic::kBirthSortCap * 4;
         h->lds = std::max(pass_lds, epi_lds);

@@ -108,13 +108,12 @@ __device__ __forceinline__ void wait_memory_complete() {
 }
 
 // LDS counter slots of one workgroup
-enum : int { kCntAbs = 0, kCntColl = 4, kCntViol = 20, kCntErr = 22, kCntQueue = 23, kCntLast = 31, kCntSlots = 32 };
+enum : int { kCntAbs = 0, kCntColl = 4, kCntViol = 20, kCntErr = 22, kCntLast = 31, kCntSlots = 32 };
 
 // LDS of one workgroup of the particle pass.  A workgroup handles one species at a time:
 // Q holds that species' deposit and M its second moment quantity (electron energy or ion
-// v_x), U the electron null-collision bounds.  Collision candidates wait in a queue
-// (structure of arrays, 1.5 x blockDim entries) until more than half a workgroup of them
-// can be processed together.
+// v_x), U the electron null-collision bounds.  Collision candidates wait in per-wave
+// queues (structure of arrays) until a full wave of them can be processed together.
 struct Lds {
     uint32_t* cnt;
     unsigned long long* Q;   // fixed-point deposit
@@ -122,12 +121,8 @@ struct Lds {
     float* E;
     float* U;                // kNullBins + 1
     uint32_t* qslot;
-    uint32_t* qid;
     uint32_t* qr;            // second Philox word of the collision draw
-    float* qx;
-    float* qvx;
-    float* qvy;
-    float* qvz;
+    float* qvx;              // completed v_x
 };
 
 // After the drift of an ionisation product: absorb at the electrodes (Sec. 2.5, ties
@@ -405,19 +400,20 @@ __device__ __forceinline__ bool stream_particle(const Params& P, const Lds& L, i
 
 // Null-collision MCC of one queued candidate (Sec. 2.5), then finish it.
 template <int MODE, int S>
-__device__ __forceinline__ void collide_entry(const Params& P, const Lds& L, int64_t i, float x, float vx,
-                                              float vy, float vz, uint32_t pid, uint32_t rword, uint32_t stepf,
-                                              unsigned cur, int64_t ns0, int64_t ns1, bool sample, float& tq,
-                                              float& tm, float& m2) {
+__device__ __forceinline__ void collide_entry(const Params& P, const Lds& L, int64_t i, float vx, uint32_t rword,
+                                              uint32_t stepf, unsigned cur, int64_t ns0, int64_t ns1, bool sample,
+                                              float& tq, float& tm, float& m2) {
+    // the queue keeps the slot, the completed v_x and the second Philox word; the rest of
+    // the state is still unchanged in memory
+    const float x = P.x[cur][S][i];
+    const uint32_t pid = P.id[cur][S][i];
+    float vy = P.vy[cur][S][i];
+    float vz = P.vz[cur][S][i];
     int j;
     float w;
     cell_of(x, P.n_cells, j, w);
     const float E = fmaf(w, L.E[j + 1] - L.E[j], L.E[j]);
     const float kE = P.kick[S] * E;
-    if (S == 1) {   // ions read vy, vz only when they are candidates
-        vy = P.vy[cur][1][i];
-        vz = P.vz[cur][1][i];
-    }
     int8_t code = 1;
     bool dirty = false;
     float vtx = 0.0f, vty = 0.0f, vtz = 0.0f;
@@ -509,35 +505,44 @@ __device__ __forceinline__ void collide_entry(const Params& P, const Lds& L, int
     finish<MODE, S>(P, L, i, x, vx, vy, vz, dirty, kE, sample, cur, tq, tm, m2);
 }
 
-// Process the top `count` queued candidates, one per thread, then pop them.
+// Each wave queues its own collision candidates in LDS (kWaveQueue entries) and processes
+// them a full wave at a time, so the long MCC path runs on dense waves and the particle
+// loop needs no workgroup barrier.  Entries are written and read by the same wave, whose
+// LDS operations complete in order; the wavefront fences keep the compiler from moving
+// them across each other.
+constexpr int kWaveQueue = 128;
+
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Process queue entries [n - count, n) of this wave, one per lane (count <= 64).
 template <int MODE, int S>
-__device__ __forceinline__ void drain_queue(const Params& P, const Lds& L, unsigned count, uint32_t stepf,
-                                            unsigned cur, int64_t ns0, int64_t ns1, bool sample) {
-    const unsigned tid = threadIdx.x;
-    const unsigned n = L.cnt[kCntQueue];
+__device__ __forceinline__ void drain_queue(const Params& P, const Lds& L, int wq, unsigned n, unsigned count,
+                                            uint32_t stepf, unsigned cur, int64_t ns0, int64_t ns1, bool sample) {
+    const unsigned lane = threadIdx.x & 63;
     float tq = -1.0f, tm = -1.0f, m2 = 0.0f;
-    if (tid < count) {
-        const unsigned e = n - count + tid;
-        collide_entry<MODE, S>(P, L, (int64_t)L.qslot[e], L.qx[e], L.qvx[e], L.qvy[e], L.qvz[e], L.qid[e],
-                               L.qr[e], stepf, cur, ns0, ns1, sample, tq, tm, m2);
+    wave_fence();
+    if (lane < count) {
+        const unsigned e = wq + n - count + lane;
+        collide_entry<MODE, S>(P, L, (int64_t)L.qslot[e], L.qvx[e], L.qr[e], stepf, cur, ns0, ns1, sample, tq, tm,
+                               m2);
     }
     deposit_direct(L, P.n_cells, tq);
     if (sample) moment_direct(P, L, S, tm, m2);
-    __syncthreads();
-    if (tid == 0) L.cnt[kCntQueue] = n - count;
-    __syncthreads();
+    wave_fence();
 }
 
 // Particles [begin, end) of species S, one per thread per iteration, with the next
 // iteration's loads issued before the current particle is processed (one copy of the
-// particle code per species keeps the kernel within the instruction cache).  Collision
-// candidates are compacted into the LDS queue and processed at least half a workgroup at a
-// time, so the long MCC path runs on dense waves instead of on a few lanes of every wave.
+// particle code per species keeps the kernel within the instruction cache).
 template <int MODE, int S>
 __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t begin, int64_t end, uint32_t stepf,
                                           unsigned cur, int64_t ns0, int64_t ns1, bool sample) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63;
+    const int wq = (tid >> 6) * kWaveQueue;   // this wave's queue
     const float* __restrict__ X = P.x[cur][S];
     const float* __restrict__ VX = P.vx[cur][S];
     const uint32_t* __restrict__ ID = P.id[cur][S];
@@ -549,6 +554,7 @@ __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t
     uint32_t id = 0u;
     ChargeRun qrun;
     MomentRun mrun;
+    unsigned nq = 0;   // entries in this wave's queue (wave-uniform)
     if (i < end) {
         x = X[i];
         if (MODE != kDeposit) vx = VX[i];
@@ -585,25 +591,18 @@ __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t
         if (MODE & kComplete) {
             const unsigned long long qm = __ballot(cand);
             if (qm) {
-                const int first = __builtin_ctzll(qm);
-                unsigned qb = 0;
-                if (lane == first) qb = atomicAdd(&L.cnt[kCntQueue], (unsigned)__popcll(qm));
-                qb = __shfl(qb, first, 64);
                 if (cand) {
-                    const unsigned e = qb + (unsigned)__popcll(qm & ((1ull << lane) - 1ull));
+                    const unsigned e = wq + nq + (unsigned)__popcll(qm & ((1ull << lane) - 1ull));
                     L.qslot[e] = (uint32_t)i;
-                    L.qid[e] = id;
                     L.qr[e] = rw;
-                    L.qx[e] = x;
                     L.qvx[e] = vx;
-                    L.qvy[e] = vy;
-                    L.qvz[e] = vz;
+                }
+                nq += (unsigned)__popcll(qm);
+                if (nq >= 64u) {
+                    drain_queue<MODE, S>(P, L, wq, nq, 64u, stepf, cur, ns0, ns1, sample);
+                    nq -= 64u;
                 }
             }
-            __syncthreads();
-            const unsigned waiting = L.cnt[kCntQueue];
-            if (waiting > (unsigned)(nt / 2))
-                drain_queue<MODE, S>(P, L, min(waiting, (unsigned)nt), stepf, cur, ns0, ns1, sample);
         }
         i = inext;
         x = xn;
@@ -616,11 +615,7 @@ __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t
         flush_run(L, qrun);
         if (sample) flush_run(L, mrun);
     }
-    if (MODE & kComplete) {
-        __syncthreads();
-        const unsigned left = L.cnt[kCntQueue];
-        if (left > 0) drain_queue<MODE, S>(P, L, left, stepf, cur, ns0, ns1, sample);
-    }
+    if ((MODE & kComplete) && nq > 0u) drain_queue<MODE, S>(P, L, wq, nq, nq, stepf, cur, ns0, ns1, sample);
 }
 
 // ----------------------------------------------------------------------------------
@@ -930,14 +925,10 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     L.M = L.Q + nn;
     L.E = reinterpret_cast<float*>(L.M + nn);
     L.U = L.E + nn;
-    const int qcap = nt + nt / 2;
+    const int qcap = (nt >> 6) * kWaveQueue;
     L.qslot = reinterpret_cast<uint32_t*>(L.U + kNullBins + 1);
-    L.qid = L.qslot + qcap;
-    L.qr = L.qid + qcap;
-    L.qx = reinterpret_cast<float*>(L.qr + qcap);
-    L.qvx = L.qx + qcap;
-    L.qvy = L.qvx + qcap;
-    L.qvz = L.qvy + qcap;
+    L.qr = L.qslot + qcap;
+    L.qvx = reinterpret_cast<float*>(L.qr + qcap);
 
     const int64_t step = C->step;
     const unsigned cur = C->cur;
