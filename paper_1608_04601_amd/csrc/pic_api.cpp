@@ -395,7 +395,7 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         float* tab = nullptr;
         float* nullbound = nullptr;
         if (!dev_alloc(h, &P.ctrl, 1) || !dev_alloc(h, &P.E, nn) || !dev_alloc(h, &P.Qs, (size_t)2 * nn) ||
-            !dev_alloc(h, &P.Qdep, (size_t)2 * nn) || !dev_alloc(h, &nullbound, (size_t)pic::kNullBins + 1) ||
+            !dev_alloc(h, &nullbound, (size_t)pic::kNullBins + 1) ||
             !dev_alloc(h, &P.Q_last, nn) || !dev_alloc(h, &P.phi, nn) || !dev_alloc(h, &P.mom, (size_t)5 * nn) ||
             !dev_alloc(h, &P.birth_parent, (size_t)c.max_births_per_step) || !dev_alloc(h, &tab, std::max<size_t>(ntab, 1)) ||
             !dev_alloc(h, &h->sort_cnt, (size_t)2 * nc) || !dev_alloc(h, &h->sort_cursor, (size_t)2 * nc))
@@ -464,8 +464,10 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         // queues (128 entries of three words per wave)
         const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 8 + 4) + (size_t)(pic::kNullBins + 1) * 4 +
                                 (size_t)(h->threads / 64) * 128 * 3 * 4;
-        // last workgroup: control block copy, three FP64 node arrays, scratch, birth keys
-        const size_t epi_lds = 512 + (size_t)24 * nn + 256 + (size_t)pic::kBirthSortCap * 4;
+        // last workgroup: control block copy, three FP64 node arrays, scratch, then the
+        // potential or (before the solve) the birth keys and parents
+        const size_t epi_lds = 512 + (size_t)24 * nn + 512 +
+                               std::max((size_t)8 * nn, (size_t)pic::kBirthSortCap * 8);
         h->lds = std::max(pass_lds, epi_lds);
         const int64_t total = c.n_init_super[0] + c.n_init_super[1];
         if (c.launch_blocks > 0) {
@@ -493,7 +495,6 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         c0.period_valid = 1;
         if (!hip_ok(h, hipMemcpyAsync(P.ctrl, &c0, sizeof(c0), hipMemcpyHostToDevice, h->stream), "upload ctrl") ||
             !hip_ok(h, hipMemsetAsync(P.Qs, 0, 2 * nn * sizeof(unsigned long long), h->stream), "zero Q") ||
-            !hip_ok(h, hipMemsetAsync(P.Qdep, 0, 2 * nn * sizeof(double), h->stream), "zero deposit") ||
             !hip_ok(h, hipMemsetAsync(P.mom, 0, 5 * nn * sizeof(double), h->stream), "zero moments") ||
             !hip_ok(h, hipMemsetAsync(h->sort_cnt, 0, 2 * nc * sizeof(unsigned), h->stream), "zero sort counts"))
             goto fail_init;

@@ -619,124 +619,154 @@ __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t
 }
 
 // ----------------------------------------------------------------------------------
-// Block-wide FP64 scans for the Poisson solve (one workgroup).
+// Poisson solve (one workgroup).
 // ----------------------------------------------------------------------------------
-__device__ __forceinline__ double wave_incl_scan(double v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double t = __shfl_up(v, off, 64);
-        if (lane >= off) v += t;
-    }
-    return v;
+// Running sums of a chunk of a_i: n elements, s1 = sum a_i, s2 = sum of the inclusive
+// prefix sums of a_i over the chunk.  Chunk A followed by chunk B combine to
+// (nA + nB, s1A + s1B, s2A + s2B + nB s1A).
+struct Sums2 {
+    double n, s1, s2;
+};
+
+__device__ __forceinline__ Sums2 combine(const Sums2& a, const Sums2& b) {
+    return {a.n + b.n, a.s1 + b.s1, a.s2 + b.s2 + b.n * a.s1};
 }
 
-// In-place inclusive scan of a[0..n); scratch holds >= 16 doubles.  Returns the total.
-__device__ double block_incl_scan(double* a, int n, double* scratch) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int per = (n + nt - 1) / nt;
-    const int b = min(tid * per, n), e = min(b + per, n);
-    double s = 0.0;
-    for (int i = b; i < e; ++i) s += a[i];
-    const double ws = wave_incl_scan(s);
-    const int wid = tid >> 6, lane = tid & 63, nw = nt >> 6;
-    if (lane == 63) scratch[wid] = ws;
-    __syncthreads();
-    if (wid == 0) {
-        double t = lane < nw ? scratch[lane] : 0.0;
-        t = wave_incl_scan(t);
-        if (lane < nw) scratch[lane] = t;
-    }
-    __syncthreads();
-    double run = ws - s + (wid ? scratch[wid - 1] : 0.0);
-    for (int i = b; i < e; ++i) {
-        run += a[i];
-        a[i] = run;
-    }
-    const double total = scratch[nw - 1];
-    __syncthreads();
-    return total;
+__device__ __forceinline__ Sums2 shfl_up(const Sums2& v, int off) {
+    return {__shfl_up(v.n, off, 64), __shfl_up(v.s1, off, 64), __shfl_up(v.s2, off, 64)};
 }
 
 // Poisson with phi_0 = phi0, phi_N = 0 (Sec. 2, 2.2; central differences, Sec. 2.3), on
-// node charges Qd [C/m^2] already in LDS.  D_i = phi_{i+1} - phi_i obeys
-// D_i = D_0 - (dx/eps0) sum_{k=1..i} Q_k, and sum_i D_i = -phi0 fixes D_0; phi follows from
-// a second prefix sum.  Boundary fields by Gauss's law over the half cells next to the
-// electrodes.  Writes phi (FP64) and E (FP32) to global memory; returns E_0 and E_N.
-__device__ void solve_field(const Params& P, const double* Qd, double* work, double* phis, double* scratch,
-                            double phi0, double& E0, double& EN) {
+// node charges Qd [C/m^2] in LDS.  With D_i = phi_{i+1} - phi_i the difference equations
+// read D_i = D_0 - (dx/eps0) S1_i, S1_i = sum_{k=1..i} Q_k, so
+// phi_i = phi0 + i D_0 - (dx/eps0) S2_i with S2_i = sum_{k<i} S1_k, and phi_N = 0 fixes
+// D_0 = ((dx/eps0) S2_N - phi0) / N.  One workgroup scan of (n, S1, S2) gives both sums.
+// Boundary fields by Gauss's law over the half cells next to the electrodes.  Writes phi
+// (FP64, also to phis in LDS) and E (FP32) to global memory; returns E_0 and E_N.
+__device__ void solve_field(const Params& P, const double* Qd, double* phis, double* scratch, double phi0,
+                            double& E0, double& EN) {
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
     const int nc = P.n_cells, nn = nc + 1;
     const double dxe = P.dx_d / P.eps0;
-    for (int i = tid; i < nc; i += nt) work[i] = (i >= 1) ? Qd[i] : 0.0;
+    // a_i = Q_i for 1 <= i < nc, a_0 = 0; thread tid owns a contiguous chunk
+    const int per = (nc + nt - 1) / nt;
+    const int b = min(tid * per, nc), e = min(b + per, nc);
+    Sums2 loc{(double)(e - b), 0.0, 0.0};
+    for (int i = b; i < e; ++i) {
+        loc.s1 += (i >= 1) ? Qd[i] : 0.0;
+        loc.s2 += loc.s1;
+    }
+    Sums2 inc = loc;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const Sums2 t = shfl_up(inc, off);
+        if (lane >= off) inc = combine(t, inc);
+    }
+    Sums2* wsum = reinterpret_cast<Sums2*>(scratch);   // nw <= 16 entries
+    if (lane == 63) wsum[wid] = inc;
     __syncthreads();
-    block_incl_scan(work, nc, scratch);   // work[i] = sum_{k=1..i} Q_k, i < nc
-    double sp = 0.0;
-    for (int i = tid; i < nc; i += nt) sp += work[i];
-    for (int off = 32; off > 0; off >>= 1) sp += __shfl_xor(sp, off, 64);
-    if ((tid & 63) == 0) scratch[tid >> 6] = sp;
-    __syncthreads();
-    double S = 0.0;
-    for (int w = 0; w < (nt >> 6); ++w) S += scratch[w];
-    __syncthreads();
-    const double D0 = (dxe * S - phi0) / (double)nc;
-    for (int i = tid; i < nc; i += nt) work[i] = D0 - dxe * work[i];
-    __syncthreads();
-    block_incl_scan(work, nc, scratch);   // work[i] = sum_{k<=i} D_k
-    for (int i = tid; i < nn; i += nt) {
-        const double ph = (i == 0) ? phi0 : (i == nc ? 0.0 : phi0 + work[i - 1]);
+    Sums2 before{0.0, 0.0, 0.0}, total{0.0, 0.0, 0.0};
+    for (int w = 0; w < nw; ++w) {
+        if (w == wid) before = total;
+        total = combine(total, wsum[w]);
+    }
+    // exclusive prefix of this thread's chunk
+    Sums2 ex = shfl_up(inc, 1);
+    if (lane == 0) ex = {0.0, 0.0, 0.0};
+    ex = combine(before, ex);
+    const double D0 = (dxe * total.s2 - phi0) / (double)nc;
+    double s1 = ex.s1, s2 = ex.s2;   // S1_{i-1} and S2_i at the chunk start
+    for (int i = b; i < e; ++i) {
+        const double ph = (i == 0) ? phi0 : phi0 + (double)i * D0 - dxe * s2;
         phis[i] = ph;
         P.phi[i] = ph;
+        s1 += (i >= 1) ? Qd[i] : 0.0;
+        s2 += s1;
+    }
+    if (tid == 0) {
+        phis[nc] = 0.0;
+        P.phi[nc] = 0.0;
     }
     __syncthreads();
     const double inv2dx = 0.5 / P.dx_d, invdx = 1.0 / P.dx_d;
     for (int i = tid; i < nn; i += nt) {
-        double e;
+        double ef;
         if (i == 0)
-            e = (phis[0] - phis[1]) * invdx - Qd[0] / P.eps0;
+            ef = (phis[0] - phis[1]) * invdx - Qd[0] / P.eps0;
         else if (i == nc)
-            e = (phis[nc - 1] - phis[nc]) * invdx + Qd[nc] / P.eps0;
+            ef = (phis[nc - 1] - phis[nc]) * invdx + Qd[nc] / P.eps0;
         else
-            e = (phis[i - 1] - phis[i + 1]) * inv2dx;
-        P.E[i] = (float)e;
-        if (i == 0) scratch[16] = e;
-        if (i == nc) scratch[17] = e;
+            ef = (phis[i - 1] - phis[i + 1]) * inv2dx;
+        P.E[i] = (float)ef;
+        if (i == 0) scratch[48] = ef;
+        if (i == nc) scratch[49] = ef;
     }
     __syncthreads();
-    E0 = scratch[16];
-    EN = scratch[17];
+    E0 = scratch[48];
+    EN = scratch[49];
+}
+
+// Bitonic sort of keys[0..n2) ascending, n2 a power of two.  Element k is owned by thread
+// k % blockDim, in lane k % 64 of its wave; compare-exchange partners closer than 64 are in
+// the same wave and are exchanged with cross-lane shuffles in registers, farther ones
+// through LDS, so only strides >= 64 need a workgroup barrier.  (For n2 >= 64 every lane
+// of a wave owns an element in the same round; below, all partners are owned.)
+__device__ __forceinline__ uint32_t bitonic_lanes(uint32_t x, unsigned k, unsigned size_lo, unsigned size_hi,
+                                                  unsigned top) {
+    for (unsigned sz = size_lo; sz <= size_hi; sz <<= 1)
+        for (unsigned st = min(sz >> 1, top); st > 0; st >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)x, (int)st, 64);
+            const bool up = (k & sz) == 0;
+            const bool lower = (k & st) == 0;
+            x = (lower == up) ? min(x, o) : max(x, o);
+        }
+    return x;
+}
+
+__device__ void bitonic_sort(uint32_t* keys, unsigned n2) {
+    const unsigned tid = threadIdx.x, nt = blockDim.x;
+    if (n2 < 2) return;
+    for (unsigned k = tid; k < n2; k += nt) keys[k] = bitonic_lanes(keys[k], k, 2, min(n2, 64u), 32);
     __syncthreads();
+    for (unsigned size = 128; size <= n2; size <<= 1) {
+        for (unsigned stride = size >> 1; stride >= 64; stride >>= 1) {
+            for (unsigned t = tid; t < n2; t += nt) {
+                const unsigned partner = t ^ stride;
+                if (partner > t) {
+                    const bool up = (t & size) == 0;
+                    const uint32_t a = keys[t], c = keys[partner];
+                    if ((a > c) == up) {
+                        keys[t] = c;
+                        keys[partner] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        for (unsigned k = tid; k < n2; k += nt) keys[k] = bitonic_lanes(keys[k], k, size, size, 32);
+        __syncthreads();
+    }
 }
 
 // Ids of this launch's ionisation products: the k-th parent in ascending id order gives
-// next_id_e + k and next_id_i + k.
-__device__ void assign_birth_ids(const Params& P, uint32_t* keys, unsigned cur, int64_t ns0, int64_t ns1,
-                                 unsigned nbv, int64_t nid0, int64_t nid1) {
+// next_id_e + k and next_id_i + k.  parents[] keeps the unsorted list.
+__device__ void assign_birth_ids(const Params& P, uint32_t* keys, uint32_t* parents, unsigned cur, int64_t ns0,
+                                 int64_t ns1, unsigned nbv, int64_t nid0, int64_t nid1) {
     const int tid = threadIdx.x, nt = blockDim.x;
     if (nbv == 0) return;
     if (nbv <= (unsigned)kBirthSortCap) {
         unsigned n2 = 1;
         while (n2 < nbv) n2 <<= 1;
-        for (unsigned k = tid; k < n2; k += nt) keys[k] = k < nbv ? ld_agent(&P.birth_parent[k]) : 0xFFFFFFFFu;
-        __syncthreads();
-        for (unsigned size = 2; size <= n2; size <<= 1) {
-            for (unsigned stride = size >> 1; stride > 0; stride >>= 1) {
-                for (unsigned t = tid; t < n2; t += nt) {
-                    const unsigned partner = t ^ stride;
-                    if (partner > t) {
-                        const bool up = (t & size) == 0;
-                        const uint32_t a = keys[t], b = keys[partner];
-                        if ((a > b) == up) {
-                            keys[t] = b;
-                            keys[partner] = a;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
+        for (unsigned k = tid; k < n2; k += nt) {
+            const uint32_t p = k < nbv ? ld_agent(&P.birth_parent[k]) : 0xFFFFFFFFu;
+            keys[k] = p;
+            parents[k] = p;
         }
+        __syncthreads();
+        bitonic_sort(keys, n2);
         for (unsigned k = tid; k < nbv; k += nt) {
-            const uint32_t p = ld_agent(&P.birth_parent[k]);
+            const uint32_t p = parents[k];
             unsigned lo = 0, hi = nbv;
             while (lo < hi) {
                 const unsigned mid = (lo + hi) >> 1;
@@ -763,9 +793,11 @@ constexpr int kEpiCtrlBytes = 512;
 static_assert(sizeof(Ctrl) <= kEpiCtrlBytes && sizeof(Ctrl) % 8 == 0, "control block copy");
 constexpr int kEpiNodesPerThread = 8;   // the host keeps n_cells + 1 <= 8 * blockDim
 
-// Work of the last workgroup of a launch.  Every global value it needs is loaded in one
-// round trip (control block, charge grid, the previous potential and its window sum), the
-// bookkeeping and the Poisson solve run in LDS, and all results are stored at the end.
+// Work of the last workgroup of a launch.  The control block and the charge grid are
+// loaded in one round trip, the bookkeeping and the Poisson solve run in LDS, and all
+// results are stored at the end.  When the step just started will be sampled, the window
+// sums receive its densities (the deposit of its positions) and its potential here; its
+// completion adds the rest of the sample.
 template <int MODE>
 __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, unsigned cur, int64_t ns0,
                          int64_t ns1, bool sample) {
@@ -774,10 +806,13 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
     const int nc = P.n_cells, nn = nc + 1;
     Ctrl* cs = reinterpret_cast<Ctrl*>(smem);
     double* Qd = reinterpret_cast<double*>(smem + kEpiCtrlBytes);
-    double* work = Qd + nn;
-    double* phis = work + nn;
-    double* scratch = phis + nn;                                  // 32 doubles
-    uint32_t* keys = reinterpret_cast<uint32_t*>(scratch + 32);   // kBirthSortCap
+    double* dep0 = Qd + nn;      // this launch's deposit per species [particles]
+    double* dep1 = dep0 + nn;
+    double* scratch = dep1 + nn;                                  // 64 doubles
+    // the birth ranking is done before the solve needs phis
+    double* phis = scratch + 64;
+    uint32_t* keys = reinterpret_cast<uint32_t*>(phis);           // kBirthSortCap
+    uint32_t* parents = keys + kBirthSortCap;                     // kBirthSortCap
     constexpr bool kSolve = (MODE & (kAdvance | kDeposit)) != 0;
     constexpr int kWords = (int)(sizeof(Ctrl) / 8);
     __syncthreads();   // the particle pass is done with LDS
@@ -786,19 +821,7 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
     unsigned long long* cw = reinterpret_cast<unsigned long long*>(cs);
     unsigned long long* gw = reinterpret_cast<unsigned long long*>(C);
     for (int w = tid; w < kWords; w += nt) cw[w] = ld_agent(&gw[w]);
-    double phi_old[kEpiNodesPerThread], mom_old[kEpiNodesPerThread];
-    const bool do_phi_sample = (MODE & kComplete) && sample;
-    if (do_phi_sample) {
-#pragma unroll
-        for (int r = 0; r < kEpiNodesPerThread; ++r) {
-            const int i = tid + r * nt;
-            phi_old[r] = i < nn ? P.phi[i] : 0.0;
-            mom_old[r] = i < nn ? P.mom[4 * nn + i] : 0.0;
-        }
-    }
     if (kSolve) {
-        // this launch's deposit per species: net node charge to Qd, particle counts to
-        // work (electrons) and phis (ions) until they are stored as the next density sample
         unsigned long long q0[kEpiNodesPerThread], q1[kEpiNodesPerThread];
 #pragma unroll
         for (int r = 0; r < kEpiNodesPerThread; ++r) {
@@ -812,14 +835,14 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
             const int i = tid + r * nt;
             if (i < nn) {
                 Qd[i] = (double)((long long)q1[r] - (long long)q0[r]) * scale;
-                work[i] = (double)q0[r] * kQScaleInv;
-                phis[i] = (double)q1[r] * kQScaleInv;
+                dep0[i] = (double)q0[r] * kQScaleInv;
+                dep1[i] = (double)q1[r] * kQScaleInv;
             }
         }
     }
     __syncthreads();
 
-    // ---- completion of the previous step: births, phi sample
+    // ---- completion of the previous step: births
     if (MODE & kComplete) {
         const unsigned nb = cs->n_births;
         unsigned nbv = nb;
@@ -827,7 +850,7 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
         if ((int64_t)nbv > P.cap[0] - ns0) nbv = (unsigned)(P.cap[0] - ns0);
         if ((int64_t)nbv > P.cap[1] - ns1) nbv = (unsigned)(P.cap[1] - ns1);
         const int64_t nid0 = cs->next_id[0], nid1 = cs->next_id[1];
-        assign_birth_ids(P, keys, cur, ns0, ns1, nbv, nid0, nid1);
+        assign_birth_ids(P, keys, parents, cur, ns0, ns1, nbv, nid0, nid1);
         if (tid == 0) {
             if (nb > nbv) cs->err |= (nbv == (unsigned)P.max_births) ? kErrBirths : kErrCapacity;
             if (nid0 + nbv > 0x100000000ll || nid1 + nbv > 0x100000000ll) cs->err |= kErrIds;
@@ -842,38 +865,27 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
             cs->n_births = 0;
             if (sample) cs->n_samples += 1;
         }
-        if (do_phi_sample) {
-#pragma unroll
-            for (int r = 0; r < kEpiNodesPerThread; ++r) {
-                const int i = tid + r * nt;
-                if (i < nn) {
-                    P.mom[4 * nn + i] = mom_old[r] + phi_old[r];   // phi^n
-                    // densities at x^n: the deposit that produced x^n (the products of
-                    // this launch were added by their parents' workgroups)
-                    unsafeAtomicAdd(&P.mom[i], P.Qdep[i]);
-                    unsafeAtomicAdd(&P.mom[nn + i], P.Qdep[nn + i]);
-                }
-            }
-        }
         __syncthreads();
     }
 
     // ---- the field for the new time level
     if (kSolve) {
-        for (int r = 0; r < kEpiNodesPerThread; ++r) {
-            const int i = tid + r * nt;
-            if (i < nn) {
-                P.Qdep[i] = work[i];
-                P.Qdep[nn + i] = phis[i];
-                P.Qs[i] = 0ull;
-                P.Qs[nn + i] = 0ull;
-            }
-        }
-        __syncthreads();
         double E0, EN;
         const double t1 = (double)(step + ((MODE & kAdvance) ? 1 : 0)) * P.dt_d;
-        solve_field(P, Qd, work, phis, scratch, P.V0 * sin(P.omega * t1), E0, EN);
-        for (int i = tid; i < nn; i += nt) P.Q_last[i] = Qd[i];
+        solve_field(P, Qd, phis, scratch, P.V0 * sin(P.omega * t1), E0, EN);
+        // the step just started is sampled at its completion: densities at x^{n+1} are
+        // this launch's deposit, and phi^{n+1} was just solved for
+        const bool next_sampled = (MODE & kAdvance) && ((step + 1) % P.moments_every == 0);
+        for (int i = tid; i < nn; i += nt) {
+            P.Q_last[i] = Qd[i];
+            P.Qs[i] = 0ull;
+            P.Qs[nn + i] = 0ull;
+            if (next_sampled) {
+                unsafeAtomicAdd(&P.mom[i], dep0[i]);
+                unsafeAtomicAdd(&P.mom[nn + i], dep1[i]);
+                unsafeAtomicAdd(&P.mom[4 * nn + i], phis[i]);
+            }
+        }
         if (tid == 0) {
             if (MODE & kAdvance) {
                 unsigned long long a[2][2];

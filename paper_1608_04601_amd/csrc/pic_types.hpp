@@ -20,7 +20,7 @@ constexpr float kQScale = 16777216.0f;
 constexpr double kQScaleInv = 1.0 / 16777216.0;
 constexpr unsigned long long kQOne = 16777216ull;
 // The density moment of a sampled step is the deposit of the positions it samples (the
-// previous launch's charge deposit, kept per species).  The second moment quantity is
+// charge deposit of the launch that moved the particles there, kept per species).  The second moment quantity is
 // summed in LDS in integer fixed point (LDS integer atomics are far faster than
 // floating-point ones), in units of 1/mscale: electron energy 2^-16 eV, ion v_x 2^-8 m/s.
 // Each workgroup converts its sums to FP64 when it adds them to the window sums.
@@ -95,7 +95,6 @@ struct Params {
     Ctrl* ctrl;
     float* E;            // node field, FP32 copy for the gather [nn]
     unsigned long long* Qs;  // node deposit per species, fixed point: 2^24 per particle [2][nn]
-    double* Qdep;        // the last launch's deposit per species [particles] [2][nn]
     double* Q_last;      // charge of the last solve [C/m^2] [nn]
     double* phi;         // node potential [V] [nn]
     double* mom;         // moment window sums [5][nn]: dens_e, dens_i, energy_e, flux_i, phi
