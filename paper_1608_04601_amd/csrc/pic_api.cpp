@@ -172,7 +172,7 @@ std::vector<float> null_bounds(const pic_handle* h, const std::vector<float>& ht
     if (ne == 0) return U;
     double g2_top = 0.0;
     for (int k = 0; k < ne; ++k) {
-        const pic::ProcDev& d = P.proc[P.sp_idx[0][k]];
+        const pic::ProcDev& d = P.proc[0][k];
         const double de = 1.0 / (double)d.inv_de;
         g2_top = std::max(g2_top, (d.n - 1) * de / (double)d.efac);
     }
@@ -183,7 +183,7 @@ std::vector<float> null_bounds(const pic_handle* h, const std::vector<float>& ht
         const double lo = b * width * (1.0 - 1e-3), hi = (b + 1) * width * (1.0 + 1e-3);
         double sum = 0.0;
         for (int k = 0; k < ne; ++k) {
-            const pic::ProcDev& d = P.proc[P.sp_idx[0][k]];
+            const pic::ProcDev& d = P.proc[0][k];
             const double tlo = std::max((double)d.efac * lo, (double)d.emin) * (double)d.inv_de;
             const double thi = std::max((double)d.efac * hi, (double)d.emin) * (double)d.inv_de;
             const int k0 = std::min(std::max((int)std::floor(tlo), 0), d.n - 1);
@@ -305,7 +305,9 @@ int launch_pass_timed(pic_handle* h, int mode) {
             if (!hip_ok(h, hipEventRecord(a, h->stream), "hipEventRecord")) return h->status;
         }
     }
-    if (!hip_ok(h, pic::launch_pass(mode, h->P, h->blocks, h->threads, h->lds, h->stream), "pass_kernel launch"))
+    const int launch_mode = mode | ((h->P.dec[0] && (mode & pic::kComplete)) ? pic::kRecord : 0);
+    if (!hip_ok(h, pic::launch_pass(launch_mode, h->P, h->blocks, h->threads, h->lds, h->stream),
+                "pass_kernel launch"))
         return h->status;
     if (t && h->timing) {
         if (!hip_ok(h, hipEventRecord(b, h->stream), "hipEventRecord")) return h->status;
@@ -406,17 +408,13 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         htab.reserve(ntab);
         P.nproc = (int)h->xs.size();
         for (size_t j = 0; j < h->xs.size(); ++j) {
-            const int s = species_of_kind(h->xs[j].kind);
-            P.sp_idx[s][P.sp_n[s]++] = (int)j;
-        }
-        for (size_t j = 0; j < h->xs.size(); ++j) {
             const pic_xsec& p = h->xs[j];
-            pic::ProcDev& d = P.proc[j];
             const int s = species_of_kind(p.kind);
+            pic::ProcDev& d = P.proc[s][P.sp_n[s]++];
             const double m = h->mass[s];
             const double m_frame = p.frame == PIC_FRAME_LAB ? m : m * h->M / (m + h->M);
             d.kind = p.kind;
-            d.species = s;
+            d.idx = (int)j;
             d.n = p.n_points;
             d.off = (int)htab.size();
             d.thr = (float)p.threshold_eV;

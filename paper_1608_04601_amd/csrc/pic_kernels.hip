@@ -30,6 +30,9 @@ namespace pic {
 // ----------------------------------------------------------------------------------
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1) {
+    // The round keys are recomputed at every call (scalar adds) rather than kept live in
+    // scalar registers across the particle loop, where registers are scarce.
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
@@ -84,6 +87,13 @@ __device__ __forceinline__ void lds_count(unsigned long long* a, int j, float w)
     const unsigned long long wq = (unsigned long long)__float2int_rn(w * kQScale);   // in [0, 2^24]
     atomicAdd(&a[j], kQOne - wq);
     atomicAdd(&a[j + 1], wq);
+}
+
+// The live buffer set is picked with a uniform select: indexing the kernel-argument arrays
+// with a run-time value would copy them to private memory.
+template <typename T>
+__device__ __forceinline__ T* bufsel(T* const (&a)[2][2], unsigned cur, int s) {
+    return cur ? a[1][s] : a[0][s];
 }
 
 template <typename T>
@@ -310,27 +320,28 @@ __device__ __forceinline__ void spawn_products(const Params& P, const Lds& L, fl
             cix = absorb_or_deposit(P, L, 1, fmaf(civ[0], P.dt_over_dx, x));
         }
         const int64_t se = ns0 + k, si = ns1 + k;
-        P.x[cur][0][se] = cex;
-        P.vx[cur][0][se] = cev[0];
-        P.vy[cur][0][se] = cev[1];
-        P.vz[cur][0][se] = cev[2];
-        P.x[cur][1][si] = cix;
-        P.vx[cur][1][si] = civ[0];
-        P.vy[cur][1][si] = civ[1];
-        P.vz[cur][1][si] = civ[2];
-        if (P.dec[0]) P.dec[0][se] = 0;
-        if (P.dec[1]) P.dec[1][si] = 0;
+        bufsel(P.x, cur, 0)[se] = cex;
+        bufsel(P.vx, cur, 0)[se] = cev[0];
+        bufsel(P.vy, cur, 0)[se] = cev[1];
+        bufsel(P.vz, cur, 0)[se] = cev[2];
+        bufsel(P.x, cur, 1)[si] = cix;
+        bufsel(P.vx, cur, 1)[si] = civ[0];
+        bufsel(P.vy, cur, 1)[si] = civ[1];
+        bufsel(P.vz, cur, 1)[si] = civ[2];
+        if (MODE & kRecord) {
+            P.dec[0][se] = 0;
+            P.dec[1][si] = 0;
+        }
     }
 }
 
 // Finish a particle whose collision test (if any) is done: moment sample of the end-of-step
-// state, first half kick and drift of the next step, absorption, stores.  On return tq is
-// the position to deposit as charge (<= 0: none) and tm, m2 the position and second
-// quantity of the moment sample (tm <= 0: none); the caller deposits both wave-aggregated.
+// state, first half kick and drift of the next step, absorption.  x and vx become the values
+// to store; tq is the position to deposit as charge (<= 0: none) and tm, m2 the position and
+// second quantity of the moment sample (tm <= 0: none).
 template <int MODE, int S>
-__device__ __forceinline__ void finish(const Params& P, const Lds& L, int64_t i, float x, float vx, float vy,
-                                       float vz, bool dirty, float kE, bool sample, unsigned cur, float& tq,
-                                       float& tm, float& m2) {
+__device__ __forceinline__ void finish(const Params& P, const Lds& L, float& x, float& vx, float vy, float vz,
+                                       float kE, bool sample, float& tq, float& tm, float& m2) {
     if ((MODE & kComplete) && sample) {
         tm = x;
         m2 = S == 0 ? P.half_m_over_e[0] * (vx * vx + vy * vy + vz * vz) : vx;
@@ -339,27 +350,22 @@ __device__ __forceinline__ void finish(const Params& P, const Lds& L, int64_t i,
         vx += kE;                                  // v^{n+1/2}
         x = absorb_only(P, L, S, fmaf(vx, P.dt_over_dx, x));
         tq = x;
-        P.x[cur][S][i] = x;
-    }
-    P.vx[cur][S][i] = vx;
-    if (dirty) {
-        P.vy[cur][S][i] = vy;
-        P.vz[cur][S][i] = vz;
     }
 }
 
 // Streaming part for one particle of species S in slot i (x, vx, id and, for electrons on
 // completing launches, vy, vz loaded by the caller): gather E^n once, complete the previous
-// step's kick, and test for a collision candidate with one integer comparison.
-// Non-candidates are finished here; a candidate returns true with its completed v_x in vx and
-// the second Philox word in rword, to be queued.
+// step's kick, and test for a collision candidate with one integer comparison.  Stores
+// nothing: on return x and vx are the values for the caller to store (a hole keeps its
+// own).  Non-candidates are finished here; a candidate returns true with x unchanged, its
+// completed v_x in vx and the second Philox word in rword, to be queued.
 template <int MODE, int S>
-__device__ __forceinline__ bool stream_particle(const Params& P, const Lds& L, int64_t i, float x, float& vx,
-                                                uint32_t pid, float vy, float vz, uint32_t stepf, unsigned cur,
-                                                bool sample, float& tq, float& tm, float& m2, uint32_t& rword) {
+__device__ __forceinline__ bool stream_particle(const Params& P, const Lds& L, int64_t i, float& x, float& vx,
+                                                uint32_t pid, float vy, float vz, uint32_t stepf, bool sample,
+                                                float& tq, float& tm, float& m2, uint32_t& rword) {
     if (!(x > 0.0f)) {   // hole (or a corrupted coordinate)
         if (x != x) atomicOr(&L.cnt[kCntErr], kErrNumeric);
-        if ((MODE & kComplete) && P.dec[S]) P.dec[S][i] = 0;
+        if (MODE & kRecord) P.dec[S][i] = 0;
         return false;
     }
     if (MODE == kDeposit) {
@@ -392,9 +398,9 @@ __device__ __forceinline__ bool stream_particle(const Params& P, const Lds& L, i
             }
             code = 1;
         }
-        if (P.dec[S]) P.dec[S][i] = code;
+        if (MODE & kRecord) P.dec[S][i] = code;
     }
-    finish<MODE, S>(P, L, i, x, vx, vy, vz, false, kE, sample, cur, tq, tm, m2);
+    finish<MODE, S>(P, L, x, vx, vy, vz, kE, sample, tq, tm, m2);
     return false;
 }
 
@@ -405,10 +411,10 @@ __device__ __forceinline__ void collide_entry(const Params& P, const Lds& L, int
                                               float& tq, float& tm, float& m2) {
     // the queue keeps the slot, the completed v_x and the second Philox word; the rest of
     // the state is still unchanged in memory
-    const float x = P.x[cur][S][i];
-    const uint32_t pid = P.id[cur][S][i];
-    float vy = P.vy[cur][S][i];
-    float vz = P.vz[cur][S][i];
+    const float x = bufsel(P.x, cur, S)[i];
+    const uint32_t pid = bufsel(P.id, cur, S)[i];
+    float vy = bufsel(P.vy, cur, S)[i];
+    float vz = bufsel(P.vz, cur, S)[i];
     int j;
     float w;
     cell_of(x, P.n_cells, j, w);
@@ -433,34 +439,44 @@ __device__ __forceinline__ void collide_entry(const Params& P, const Lds& L, int
     // n_gas sigma_j [1/m] of the species' processes, four at a time with all their
     // table loads issued before any is used: zero below the threshold, energy raised
     // to the floor emin, the last point at or beyond the table end, linear
-    // interpolation in between; selection in config order
+    // interpolation in between; selection in config order.  The process table is indexed
+    // with compile-time indices only (fully unrolled), and the selected process's kind and
+    // threshold are carried in registers.
     float c = 0.0f;
-    int sel = -1;
+    int sel = -1, skind = -1;
+    float sthr = 0.0f;
     const int nsp = P.sp_n[S];
-#pragma unroll 1
-    for (int k0 = 0; k0 < nsp; k0 += 4) {
-        float ta[4], tb[4], tf[4];
-        bool tbelow[4], ttop[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (k0 + k < nsp) {
-                const ProcDev& p = P.proc[P.sp_idx[S][k0 + k]];
-                const float eps = p.efac * g2;
-                const float t = fmaxf(eps, p.emin) * p.inv_de;
-                tbelow[k] = eps < p.thr;
-                ttop[k] = t >= (float)(p.n - 1);
-                const int kk = ttop[k] ? p.n - 2 : (int)t;
-                tf[k] = t - (float)kk;
-                ta[k] = P.tab[p.off + kk];
-                tb[k] = P.tab[p.off + kk + 1];
+    for (int k0 = 0; k0 < kMaxProcPerSpecies; k0 += 4) {
+        if (k0 < nsp) {
+            float ta[4], tb[4], tf[4];
+            bool tbelow[4], ttop[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k0 + k < nsp) {
+                    const ProcDev& p = P.proc[S][k0 + k];
+                    const float eps = p.efac * g2;
+                    const float t = fmaxf(eps, p.emin) * p.inv_de;
+                    tbelow[k] = eps < p.thr;
+                    ttop[k] = t >= (float)(p.n - 1);
+                    const int kk = ttop[k] ? p.n - 2 : (int)t;
+                    tf[k] = t - (float)kk;
+                    ta[k] = P.tab[p.off + kk];
+                    tb[k] = P.tab[p.off + kk + 1];
+                }
             }
-        }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (k0 + k < nsp) {
-                const float sig = tbelow[k] ? 0.0f : (ttop[k] ? tb[k] : fmaf(tb[k] - ta[k], tf[k], ta[k]));
-                c = fmaf(sig, gm, c);
-                if (sel < 0 && R < c) sel = P.sp_idx[S][k0 + k];
+            for (int k = 0; k < 4; ++k) {
+                if (k0 + k < nsp) {
+                    const ProcDev& p = P.proc[S][k0 + k];
+                    const float sig = tbelow[k] ? 0.0f : (ttop[k] ? tb[k] : fmaf(tb[k] - ta[k], tf[k], ta[k]));
+                    c = fmaf(sig, gm, c);
+                    if (sel < 0 && R < c) {
+                        sel = p.idx;
+                        skind = p.kind;
+                        sthr = p.thr;
+                    }
+                }
             }
         }
     }
@@ -468,26 +484,25 @@ __device__ __forceinline__ void collide_entry(const Params& P, const Lds& L, int
     if (sel >= 0) {
         code = (int8_t)(2 + sel);
         atomicAdd(&L.cnt[kCntColl + sel], 1u);
-        const ProcDev& p = P.proc[sel];
         const uint4 Cw = philox(pid, 0u, stepf, ((uint32_t)S << 8) | kScatter, P.key0, P.key1);
         float n1x, n1y, n1z;
         iso_dir(Cw.x, Cw.y, n1x, n1y, n1z);
         dirty = true;
-        if (p.kind == 0 || p.kind == 3) {   // elastic / isotropic: CM-isotropic two-body
+        if (skind == 0 || skind == 3) {   // elastic / isotropic: CM-isotropic two-body
             const float fa = P.fa[S], fb = P.fb[S];
             const float sgb = fb * gm;
             vx = fmaf(sgb, n1x, fmaf(fa, vx, fb * vtx));
             vy = fmaf(sgb, n1y, fmaf(fa, vy, fb * vty));
             vz = fmaf(sgb, n1z, fmaf(fa, vz, fb * vtz));
-        } else if (S == 0 && p.kind == 1) {   // excitation: lose the threshold energy
+        } else if (S == 0 && skind == 1) {   // excitation: lose the threshold energy
             const float eps = P.half_m_over_e[0] * g2;
-            const float sp = sqrtf(fmaxf(eps - p.thr, 0.0f) * P.two_e_over_m_e);
+            const float sp = sqrtf(fmaxf(eps - sthr, 0.0f) * P.two_e_over_m_e);
             vx = sp * n1x;
             vy = sp * n1y;
             vz = sp * n1z;
-        } else if (S == 0 && p.kind == 2) {   // ionisation: equal share of eps - eps_iz
+        } else if (S == 0 && skind == 2) {   // ionisation: equal share of eps - eps_iz
             const float eps = P.half_m_over_e[0] * g2;
-            const float sp = sqrtf(fmaxf(eps - p.thr, 0.0f) * P.e_over_m_e);
+            const float sp = sqrtf(fmaxf(eps - sthr, 0.0f) * P.e_over_m_e);
             vx = sp * n1x;
             vy = sp * n1y;
             vz = sp * n1z;
@@ -501,8 +516,15 @@ __device__ __forceinline__ void collide_entry(const Params& P, const Lds& L, int
             vz = vtz;
         }
     }
-    if (P.dec[S]) P.dec[S][i] = code;
-    finish<MODE, S>(P, L, i, x, vx, vy, vz, dirty, kE, sample, cur, tq, tm, m2);
+    if (MODE & kRecord) P.dec[S][i] = code;
+    float xs = x;
+    finish<MODE, S>(P, L, xs, vx, vy, vz, kE, sample, tq, tm, m2);
+    if (MODE & kAdvance) bufsel(P.x, cur, S)[i] = xs;
+    bufsel(P.vx, cur, S)[i] = vx;
+    if (dirty) {
+        bufsel(P.vy, cur, S)[i] = vy;
+        bufsel(P.vz, cur, S)[i] = vz;
+    }
 }
 
 // Each wave queues its own collision candidates in LDS (kWaveQueue entries) and processes
@@ -534,82 +556,108 @@ __device__ __forceinline__ void drain_queue(const Params& P, const Lds& L, int w
     wave_fence();
 }
 
+// Registers of one particle as loaded by the stream.
+struct Regs {
+    float x, vx, vy, vz;
+    uint32_t id;
+};
+
+template <int MODE, int S>
+__device__ __forceinline__ Regs load_particle(const Params& P, unsigned cur, int64_t i) {
+    Regs r{-1.0f, 0.0f, 0.0f, 0.0f, 0u};
+    r.x = bufsel(P.x, cur, S)[i];
+    if (MODE != kDeposit) r.vx = bufsel(P.vx, cur, S)[i];
+    if (MODE & kComplete) r.id = bufsel(P.id, cur, S)[i];
+    if ((MODE & kComplete) && S == 0) {   // electrons need |v| for the pre-test and the energy
+        r.vy = bufsel(P.vy, cur, S)[i];
+        r.vz = bufsel(P.vz, cur, S)[i];
+    }
+    return r;
+}
+
+template <int MODE, int S>
+__device__ __forceinline__ Regs load_particle_if(const Params& P, unsigned cur, int64_t i, int64_t end) {
+    Regs r{-1.0f, 0.0f, 0.0f, 0.0f, 0u};
+    if (i < end) r = load_particle<MODE, S>(P, cur, i);
+    return r;
+}
+
+// Particle i of species S (in range when FULL) with registers r: stream it, store its x and
+// vx, deposit, and queue it if it is a collision candidate.
+template <int MODE, int S, bool FULL>
+__device__ __forceinline__ void process_particle(const Params& P, const Lds& L, int64_t i, int64_t end, Regs r,
+                                                 uint32_t stepf, unsigned cur, int64_t ns0, int64_t ns1, bool sample,
+                                                 int lane, int wq, ChargeRun& qrun, MomentRun& mrun, unsigned& nq) {
+    float tq = -1.0f, tm = -1.0f, m2 = 0.0f;
+    uint32_t rw = 0u;
+    bool cand = false;
+    if (FULL || i < end) {
+        cand = stream_particle<MODE, S>(P, L, i, r.x, r.vx, r.id, r.vy, r.vz, stepf, sample, tq, tm, m2, rw);
+        if (MODE & kAdvance) bufsel(P.x, cur, S)[i] = r.x;
+        if (MODE != kDeposit) bufsel(P.vx, cur, S)[i] = r.vx;
+    }
+    if (S == 0) {   // electrons leave cell order within a step or two
+        deposit_direct(L, P.n_cells, tq);
+        if (sample) moment_direct(P, L, S, tm, m2);
+    } else {
+        deposit_run(L, P.n_cells, qrun, tq);
+        if (sample) moment_run(P, L, S, mrun, tm, m2);
+    }
+    if (MODE & kComplete) {
+        const unsigned long long qm = __ballot(cand);
+        if (qm) {
+            if (cand) {
+                const unsigned e = wq + nq + (unsigned)__popcll(qm & ((1ull << lane) - 1ull));
+                L.qslot[e] = (uint32_t)i;
+                L.qr[e] = rw;
+                L.qvx[e] = r.vx;
+            }
+            nq += (unsigned)__popcll(qm);
+            if (nq >= 64u) {
+                drain_queue<MODE, S>(P, L, wq, nq, 64u, stepf, cur, ns0, ns1, sample);
+                nq -= 64u;
+            }
+        }
+    }
+}
+
 // Particles [begin, end) of species S, one per thread per iteration, with the next
 // iteration's loads issued before the current particle is processed (one copy of the
-// particle code per species keeps the kernel within the instruction cache).
+// particle code per species keeps the kernel within the instruction cache).  While both the
+// current and the next iteration cover every lane, loads and stores are unconditional, so
+// the wait for the current particle's data does not also wait for the next one's loads.
 template <int MODE, int S>
 __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t begin, int64_t end, uint32_t stepf,
                                           unsigned cur, int64_t ns0, int64_t ns1, bool sample) {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63;
-    const int wq = (tid >> 6) * kWaveQueue;   // this wave's queue
-    const float* __restrict__ X = P.x[cur][S];
-    const float* __restrict__ VX = P.vx[cur][S];
-    const uint32_t* __restrict__ ID = P.id[cur][S];
-    const float* __restrict__ VY = P.vy[cur][S];
-    const float* __restrict__ VZ = P.vz[cur][S];
-    constexpr bool kPreloadYZ = (MODE & kComplete) && S == 0;
-    int64_t i = begin + tid;
-    float x = -1.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
-    uint32_t id = 0u;
+    const int lane = tid & 63, wq = (tid >> 6) * kWaveQueue;
     ChargeRun qrun;
     MomentRun mrun;
     unsigned nq = 0;   // entries in this wave's queue (wave-uniform)
-    if (i < end) {
-        x = X[i];
-        if (MODE != kDeposit) vx = VX[i];
-        if (MODE & kComplete) id = ID[i];
-        if (kPreloadYZ) {
-            vy = VY[i];
-            vz = VZ[i];
+    const int64_t nfull = (end - begin) / nt;   // iterations in which every lane has a particle
+    int64_t i = begin + tid;
+    if (nfull >= 2) {
+        Regs r = load_particle<MODE, S>(P, cur, i);
+        for (int64_t it = 0; it + 1 < nfull; ++it) {
+            const Regs rn = load_particle<MODE, S>(P, cur, i + nt);
+            process_particle<MODE, S, true>(P, L, i, end, r, stepf, cur, ns0, ns1, sample, lane, wq, qrun, mrun, nq);
+            r = rn;
+            i += nt;
         }
-    }
-    for (int64_t base = begin; base < end; base += nt) {
-        const int64_t inext = i + nt;
-        float xn = -1.0f, vxn = 0.0f, vyn = 0.0f, vzn = 0.0f;
-        uint32_t idn = 0u;
-        if (inext < end) {
-            xn = X[inext];
-            if (MODE != kDeposit) vxn = VX[inext];
-            if (MODE & kComplete) idn = ID[inext];
-            if (kPreloadYZ) {
-                vyn = VY[inext];
-                vzn = VZ[inext];
-            }
+        // iteration nfull - 1, whose successor is the ragged tail (possibly empty)
+        const Regs rn = load_particle_if<MODE, S>(P, cur, i + nt, end);
+        process_particle<MODE, S, true>(P, L, i, end, r, stepf, cur, ns0, ns1, sample, lane, wq, qrun, mrun, nq);
+        i += nt;
+        process_particle<MODE, S, false>(P, L, i, end, rn, stepf, cur, ns0, ns1, sample, lane, wq, qrun, mrun, nq);
+    } else {
+        Regs r = load_particle_if<MODE, S>(P, cur, i, end);
+        for (int64_t base = begin; base < end; base += nt) {
+            const Regs rn = load_particle_if<MODE, S>(P, cur, i + nt, end);
+            process_particle<MODE, S, false>(P, L, i, end, r, stepf, cur, ns0, ns1, sample, lane, wq, qrun, mrun,
+                                             nq);
+            r = rn;
+            i += nt;
         }
-        float tq = -1.0f, tm = -1.0f, m2 = 0.0f;
-        uint32_t rw = 0u;
-        bool cand = false;
-        if (i < end) cand = stream_particle<MODE, S>(P, L, i, x, vx, id, vy, vz, stepf, cur, sample, tq, tm, m2, rw);
-        if (S == 0) {   // electrons leave cell order within a step or two
-            deposit_direct(L, P.n_cells, tq);
-            if (sample) moment_direct(P, L, S, tm, m2);
-        } else {
-            deposit_run(L, P.n_cells, qrun, tq);
-            if (sample) moment_run(P, L, S, mrun, tm, m2);
-        }
-        if (MODE & kComplete) {
-            const unsigned long long qm = __ballot(cand);
-            if (qm) {
-                if (cand) {
-                    const unsigned e = wq + nq + (unsigned)__popcll(qm & ((1ull << lane) - 1ull));
-                    L.qslot[e] = (uint32_t)i;
-                    L.qr[e] = rw;
-                    L.qvx[e] = vx;
-                }
-                nq += (unsigned)__popcll(qm);
-                if (nq >= 64u) {
-                    drain_queue<MODE, S>(P, L, wq, nq, 64u, stepf, cur, ns0, ns1, sample);
-                    nq -= 64u;
-                }
-            }
-        }
-        i = inext;
-        x = xn;
-        vx = vxn;
-        vy = vyn;
-        vz = vzn;
-        id = idn;
     }
     if (S == 1) {
         flush_run(L, qrun);
@@ -772,8 +820,8 @@ __device__ void assign_birth_ids(const Params& P, uint32_t* keys, uint32_t* pare
                 const unsigned mid = (lo + hi) >> 1;
                 if (keys[mid] < p) lo = mid + 1; else hi = mid;
             }
-            P.id[cur][0][ns0 + k] = (uint32_t)(nid0 + lo);
-            P.id[cur][1][ns1 + k] = (uint32_t)(nid1 + lo);
+            bufsel(P.id, cur, 0)[ns0 + k] = (uint32_t)(nid0 + lo);
+            bufsel(P.id, cur, 1)[ns1 + k] = (uint32_t)(nid1 + lo);
         }
         __syncthreads();
     } else {
@@ -781,8 +829,8 @@ __device__ void assign_birth_ids(const Params& P, uint32_t* keys, uint32_t* pare
             const uint32_t p = ld_agent(&P.birth_parent[k]);
             unsigned rank = 0;
             for (unsigned q = 0; q < nbv; ++q) rank += ld_agent(&P.birth_parent[q]) < p;
-            P.id[cur][0][ns0 + k] = (uint32_t)(nid0 + rank);
-            P.id[cur][1][ns1 + k] = (uint32_t)(nid1 + rank);
+            bufsel(P.id, cur, 0)[ns0 + k] = (uint32_t)(nid0 + rank);
+            bufsel(P.id, cur, 1)[ns1 + k] = (uint32_t)(nid1 + rank);
         }
         __syncthreads();
     }
@@ -1192,6 +1240,12 @@ __global__ void reset_window_kernel(Params P) {
 // ----------------------------------------------------------------------------------
 hipError_t launch_pass(int mode, const Params& P, int blocks, int threads, size_t lds, hipStream_t st) {
     switch (mode) {
+        case kComplete | kAdvance | kRecord:
+            hipLaunchKernelGGL(pass_kernel<kComplete | kAdvance | kRecord>, dim3(blocks), dim3(threads), lds, st, P);
+            break;
+        case kComplete | kRecord:
+            hipLaunchKernelGGL(pass_kernel<kComplete | kRecord>, dim3(blocks), dim3(threads), lds, st, P);
+            break;
         case kComplete | kAdvance:
             hipLaunchKernelGGL(pass_kernel<kComplete | kAdvance>, dim3(blocks), dim3(threads), lds, st, P);
             break;
@@ -1248,6 +1302,12 @@ hipError_t set_pass_lds_limit(size_t bytes) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kDeposit>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete | kAdvance | kRecord>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete | kRecord>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, b);
     return e;
 }

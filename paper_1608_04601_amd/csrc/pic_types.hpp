@@ -34,6 +34,7 @@ constexpr int kNullBins = 256;
 constexpr int kComplete = 1;   // finish the previous step: second half kick, MCC, births, moments
 constexpr int kAdvance = 2;    // start the next step: first half kick, drift, absorb, deposit, solve
 constexpr int kDeposit = 4;    // deposit only and solve at the current time (load / set_particles)
+constexpr int kRecord = 8;     // with kComplete: write the per-slot collision decision record
 
 // device error bits
 constexpr uint32_t kErrCapacity = 1u;   // particle storage exhausted by births
@@ -75,7 +76,7 @@ struct Ctrl {
 
 struct ProcDev {
     int32_t kind;
-    int32_t species;
+    int32_t idx;        // index in the configuration (collision counters, decision codes)
     int32_t n;          // table points
     int32_t off;        // offset into the table array
     float thr;          // threshold [eV]
@@ -105,9 +106,8 @@ struct Params {
     const float* nullbound;   // [kNullBins + 1] electron collision-frequency bounds [1/s]
     float inv_gbin;           // bins per unit g^2 [s^2/m^2]
     float pad1;
-    ProcDev proc[kMaxProc];
+    ProcDev proc[2][kMaxProcPerSpecies];      // processes of each species, in config order
     int32_t sp_n[2];                          // processes per species
-    int32_t sp_idx[2][kMaxProcPerSpecies];    // their table indices, in config order
     int32_t nproc;
     int32_t n_cells;
     int32_t max_births;
