@@ -75,7 +75,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="production", choices=sorted(workloads_by_name()))
-    ap.add_argument("--cpu-steps", type=int, default=16, help="oracle steps of the CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=20, help="oracle steps of the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-blocks", type=int, default=0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,

@@ -100,6 +100,12 @@ typedef struct pic_config {
     int32_t moments_every;      /* moment sample every this many steps, >= 1           */
     int32_t max_births_per_step;/* ionisations one step may create, >= 1               */
     int32_t launch_blocks;      /* workgroups of the particle pass; 0 = automatic      */
+    int32_t electron_order;     /* periodic reordering of the electrons: 1 = sort by cell,
+                                   0 = only remove absorbed slots (order kept), -1 = automatic:
+                                   sort when a 3 eV thermal electron crosses at most 16 cells per
+                                   sort interval.  Ions are always sorted by cell.  Results do
+                                   not depend on this choice. */
+    int32_t reserved;           /* must be 0                                           */
 } pic_config;
 
 /* Window averages since the last reset (pic_moments).  Arrays are caller-owned host

@@ -40,7 +40,8 @@ class pic_config(C.Structure):
                 ("ti_init_eV", C.c_double), ("n_cells", C.c_int32), ("n_xsec", C.c_int32),
                 ("xsec", C.POINTER(pic_xsec)), ("n_init_super", C.c_int64 * 2), ("capacity", C.c_int64 * 2),
                 ("seed", C.c_uint64), ("sort_every", C.c_int32), ("moments_every", C.c_int32),
-                ("max_births_per_step", C.c_int32), ("launch_blocks", C.c_int32)]
+                ("max_births_per_step", C.c_int32), ("launch_blocks", C.c_int32),
+                ("electron_order", C.c_int32), ("reserved", C.c_int32)]
 
 
 class pic_moments_out(C.Structure):
@@ -148,6 +149,7 @@ class Config:
         c.seed = int(disc.seed) & 0xFFFFFFFFFFFFFFFF
         c.sort_every, c.moments_every = int(disc.sort_every), int(disc.moments_every)
         c.max_births_per_step, c.launch_blocks = int(disc.max_births_per_step), int(launch_blocks)
+        c.electron_order, c.reserved = int(getattr(disc, "electron_order", -1)), 0
         self.c = c
 
 

@@ -226,6 +226,8 @@ std::string validate(const pic_config* c) {
     if (c->moments_every < 1) return "moments_every must be >= 1";
     if (c->max_births_per_step < 1) return "max_births_per_step must be >= 1";
     if (c->launch_blocks < 0 || c->launch_blocks > 65536) return "launch_blocks must be in [0, 65536]";
+    if (c->electron_order < -1 || c->electron_order > 1) return "electron_order must be -1, 0 or 1";
+    if (c->reserved != 0) return "reserved must be 0";
     int per_species[2] = {0, 0};
     for (int j = 0; j < c->n_xsec; ++j) {
         const pic_xsec& p = c->xsec[j];
@@ -400,7 +402,8 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
             !dev_alloc(h, &nullbound, (size_t)pic::kNullBins + 1) ||
             !dev_alloc(h, &P.Q_last, nn) || !dev_alloc(h, &P.phi, nn) || !dev_alloc(h, &P.mom, (size_t)5 * nn) ||
             !dev_alloc(h, &P.birth_parent, (size_t)c.max_births_per_step) || !dev_alloc(h, &tab, std::max<size_t>(ntab, 1)) ||
-            !dev_alloc(h, &h->sort_cnt, (size_t)2 * nc) || !dev_alloc(h, &h->sort_cursor, (size_t)2 * nc))
+            !dev_alloc(h, &h->sort_cnt, (size_t)2 * nc + pic::kMaxSortBlocks) ||
+            !dev_alloc(h, &h->sort_cursor, (size_t)2 * nc + pic::kMaxSortBlocks))
             goto fail_init;
         P.tab = tab;
         P.nullbound = nullbound;
@@ -451,6 +454,15 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         P.V0 = c.rf_voltage_V;
         P.omega = 2.0 * kPi * c.rf_frequency_Hz;
         P.dt_d = c.dt_s;
+        // periodic reordering: ions by cell; electrons by cell only while they stay near
+        // their cell over a sort interval (else cell order is lost within a few steps and
+        // the sort's scattered writes cost more than it saves)
+        {
+            const double v3 = std::sqrt(3.0 * kE0 / kMe);
+            const double cells = (double)std::max(c.sort_every, 1) * c.dt_s * v3 / h->dx;
+            P.sort_cells[0] = c.electron_order == 1 || (c.electron_order == -1 && cells <= 16.0);
+            P.sort_cells[1] = 1;
+        }
         P.mscale[0] = pic::kMomScaleE;
         P.mscale[1] = pic::kMomScaleI;
 
@@ -474,8 +486,8 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
             const int64_t per_block = (int64_t)h->threads * 8;
             h->blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (total + per_block - 1) / per_block));
         }
-        h->sort_threads = nc > 1024 ? 1024 : 256;
-        h->sort_blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (total + 8191) / 8192));
+        h->sort_threads = 1024;
+        h->sort_blocks = (int)std::min<int64_t>(pic::kMaxSortBlocks, std::max<int64_t>(2, (total + 8191) / 8192));
         if (!hip_ok(h, pic::set_pass_lds_limit(h->lds), "hipFuncSetAttribute")) goto fail_init;
 
         if (!hip_ok(h, hipMemcpyAsync(tab, htab.data(), htab.size() * sizeof(float), hipMemcpyHostToDevice, h->stream),
@@ -494,7 +506,8 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         if (!hip_ok(h, hipMemcpyAsync(P.ctrl, &c0, sizeof(c0), hipMemcpyHostToDevice, h->stream), "upload ctrl") ||
             !hip_ok(h, hipMemsetAsync(P.Qs, 0, 2 * nn * sizeof(unsigned long long), h->stream), "zero Q") ||
             !hip_ok(h, hipMemsetAsync(P.mom, 0, 5 * nn * sizeof(double), h->stream), "zero moments") ||
-            !hip_ok(h, hipMemsetAsync(h->sort_cnt, 0, 2 * nc * sizeof(unsigned), h->stream), "zero sort counts"))
+            !hip_ok(h, hipMemsetAsync(h->sort_cnt, 0, (2 * nc + pic::kMaxSortBlocks) * sizeof(unsigned), h->stream),
+                    "zero sort counts"))
             goto fail_init;
         const double temps[2] = {c.te_init_eV, c.ti_init_eV};
         for (int s = 0; s < 2; ++s) {

@@ -1099,109 +1099,205 @@ __global__ void load_kernel(Params P, int s, int64_t n, double vth) {
 }
 
 // ----------------------------------------------------------------------------------
-// Periodic cell sort + compaction (performance only; results do not depend on the
-// order because every random number is keyed by particle id).
+// Periodic reordering (performance only; results do not depend on the order because
+// every random number is keyed by particle id and the deposits are exact).  A species is
+// either sorted by cell (ions, which move a small fraction of a cell per step, keeping the
+// per-lane run caches of the particle pass effective; electrons when they stay near
+// their cell over a sort interval) or only compacted: absorbed slots removed, order kept,
+// which streams.  Counters: cnt[s nc + j] count of cell j of species s (cell sort),
+// cnt[2 nc + b] alive particles of block b (compaction); cursor[] holds the matching
+// exclusive prefix sums.
 // ----------------------------------------------------------------------------------
-__global__ void sort_count_kernel(Params P, unsigned* cnt) {
+// Blocks [0, Ge) take contiguous electron ranges, [Ge, G) ion ranges (G >= 2 when both
+// species have slots).
+__device__ __forceinline__ void sort_split(int G, int b, int64_t ns0, int64_t ns1, int& s, int& Ge, int64_t& begin,
+                                           int64_t& end) {
+    const int64_t total = ns0 + ns1;
+    Ge = total > 0 ? (int)(((double)G * (double)ns0) / (double)total + 0.5) : G / 2;
+    if (ns0 > 0) Ge = max(Ge, 1);
+    if (ns1 > 0) Ge = min(Ge, G - 1);
+    if (ns1 == 0) Ge = G;
+    if (b < Ge) {
+        s = 0;
+        const int64_t per = (ns0 + Ge - 1) / max(Ge, 1);
+        begin = min((int64_t)b * per, ns0);
+        end = min(begin + per, ns0);
+    } else {
+        s = 1;
+        const int Gi = G - Ge;
+        const int64_t per = (ns1 + Gi - 1) / max(Gi, 1);
+        begin = min((int64_t)(b - Ge) * per, ns1);
+        end = min(begin + per, ns1);
+    }
+}
+
+__global__ void __launch_bounds__(1024) sort_count_kernel(Params P, unsigned* cnt) {
     extern __shared__ __align__(16) unsigned char smem[];
-    unsigned* h = reinterpret_cast<unsigned*>(smem);
+    unsigned* h = reinterpret_cast<unsigned*>(smem);   // nc cell counts, then one alive count
     const int nc = P.n_cells, tid = threadIdx.x, nt = blockDim.x;
     const Ctrl* C = P.ctrl;
     const unsigned cur = C->cur;
-    const int64_t ns0 = C->n_slots[0], ns1 = C->n_slots[1];
-    for (int i = tid; i < 2 * nc; i += nt) h[i] = 0;
+    int s, Ge;
+    int64_t begin, end;
+    sort_split(gridDim.x, blockIdx.x, C->n_slots[0], C->n_slots[1], s, Ge, begin, end);
+    for (int i = tid; i <= nc; i += nt) h[i] = 0;
     __syncthreads();
-    const int64_t total = ns0 + ns1;
-    for (int64_t v = (int64_t)blockIdx.x * nt + tid; v < total; v += (int64_t)gridDim.x * nt) {
-        const int s = v >= ns0;
-        const float x = P.x[cur][s][s ? v - ns0 : v];
-        if (x > 0.0f) {
-            int j;
-            float w;
-            cell_of(x, nc, j, w);
-            atomicAdd(&h[s * nc + j], 1u);
+    const float* X = bufsel(P.x, cur, s);
+    if (!P.sort_cells[s]) {
+        unsigned c = 0;
+        for (int64_t v = begin + tid; v < end; v += nt) c += X[v] > 0.0f ? 1u : 0u;
+        if (c) atomicAdd(&h[nc], c);
+        __syncthreads();
+        if (tid == 0) cnt[2 * nc + blockIdx.x] = h[nc];
+    } else {
+        for (int64_t v = begin + tid; v < end; v += nt) {
+            const float x = X[v];
+            if (x > 0.0f) {
+                int j;
+                float w;
+                cell_of(x, nc, j, w);
+                atomicAdd(&h[j], 1u);
+            }
         }
+        __syncthreads();
+        for (int i = tid; i < nc; i += nt)
+            if (h[i]) atomicAdd(&cnt[s * nc + i], h[i]);
     }
-    __syncthreads();
-    for (int i = tid; i < 2 * nc; i += nt)
-        if (h[i]) atomicAdd(&cnt[i], h[i]);
 }
 
-__global__ void sort_scan_kernel(Params P, unsigned* cnt, unsigned* cursor) {
+// Exclusive scan of a[0..n) into o (one block of 1024 threads); a is cleared.  Returns the
+// total to every thread.
+__device__ unsigned block_excl_scan(unsigned* a, unsigned* o, int n, unsigned* sh) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int per = (n + nt - 1) / nt;
+    const int b = min(tid * per, n), e = min(b + per, n);
+    unsigned sum = 0;
+    for (int i = b; i < e; ++i) sum += a[i];
+    sh[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        const unsigned t = tid >= off ? sh[tid - off] : 0u;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    unsigned run = sh[tid] - sum;
+    for (int i = b; i < e; ++i) {
+        o[i] = run;
+        run += a[i];
+        a[i] = 0;
+    }
+    const unsigned total = sh[nt - 1];
+    __syncthreads();
+    return total;
+}
+
+__global__ void __launch_bounds__(1024) sort_scan_kernel(Params P, unsigned* cnt, unsigned* cursor, int G) {
     __shared__ unsigned sh[1024];
-    const int nc = P.n_cells, tid = threadIdx.x, nt = blockDim.x;
-    for (int s = 0; s < 2; ++s) {
-        unsigned* c = cnt + s * nc;
-        unsigned* o = cursor + s * nc;
-        const int per = (nc + nt - 1) / nt;
-        const int b = min(tid * per, nc), e = min(b + per, nc);
-        unsigned sum = 0;
-        for (int i = b; i < e; ++i) sum += c[i];
-        sh[tid] = sum;
-        __syncthreads();
-        for (int off = 1; off < nt; off <<= 1) {
-            const unsigned t = tid >= off ? sh[tid - off] : 0u;
-            __syncthreads();
-            sh[tid] += t;
-            __syncthreads();
-        }
-        unsigned run = sh[tid] - sum;
-        for (int i = b; i < e; ++i) {
-            o[i] = run;
-            run += c[i];
-            c[i] = 0;
-        }
-        if (tid == nt - 1) P.ctrl->sort_alive[s] = sh[nt - 1];
-        __syncthreads();
+    const int nc = P.n_cells;
+    Ctrl* C = P.ctrl;
+    int s, Ge;
+    int64_t begin, end;
+    sort_split(G, 0, C->n_slots[0], C->n_slots[1], s, Ge, begin, end);
+    unsigned alive[2];
+    for (int q = 0; q < 2; ++q) {
+        if (P.sort_cells[q])
+            alive[q] = block_excl_scan(cnt + q * nc, cursor + q * nc, nc, sh);
+        else if (q == 0)
+            alive[q] = block_excl_scan(cnt + 2 * nc, cursor + 2 * nc, Ge, sh);
+        else
+            alive[q] = block_excl_scan(cnt + 2 * nc + Ge, cursor + 2 * nc + Ge, G - Ge, sh);
+    }
+    if (threadIdx.x == 0) {
+        C->sort_alive[0] = alive[0];
+        C->sort_alive[1] = alive[1];
     }
 }
 
 __global__ void __launch_bounds__(1024) sort_scatter_kernel(Params P, unsigned* cursor) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nc = P.n_cells, tid = threadIdx.x, nt = blockDim.x;
-    unsigned* h = reinterpret_cast<unsigned*>(smem);   // 2 nc local counts, then cursors
-    unsigned* base = h + 2 * nc;                        // 2 nc reserved bases
-    unsigned* flag = base + 2 * nc;
+    const int lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
+    unsigned* h = reinterpret_cast<unsigned*>(smem);   // nc local counts, then cursors
+    unsigned* base = h + nc;                            // nc reserved bases
+    unsigned* wcnt = base + nc;                         // 16 wave counts
+    unsigned* flag = wcnt + 16;
     Ctrl* C = P.ctrl;
     const unsigned cur = C->cur, nxt = cur ^ 1u;
-    const int64_t ns0 = C->n_slots[0], ns1 = C->n_slots[1];
-    for (int i = tid; i < 2 * nc; i += nt) h[i] = 0;
-    __syncthreads();
-    const int64_t total = ns0 + ns1;
-    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-    const int64_t begin = (int64_t)blockIdx.x * per;
-    const int64_t end = min(begin + per, total);
-    for (int64_t v = begin + tid; v < end; v += nt) {
-        const int s = v >= ns0;
-        const float x = P.x[cur][s][s ? v - ns0 : v];
-        if (x > 0.0f) {
-            int j;
-            float w;
-            cell_of(x, nc, j, w);
-            atomicAdd(&h[s * nc + j], 1u);
+    int s, Ge;
+    int64_t begin, end;
+    sort_split(gridDim.x, blockIdx.x, C->n_slots[0], C->n_slots[1], s, Ge, begin, end);
+    const float* X = bufsel(P.x, cur, s);
+    const float* VX = bufsel(P.vx, cur, s);
+    const float* VY = bufsel(P.vy, cur, s);
+    const float* VZ = bufsel(P.vz, cur, s);
+    const uint32_t* ID = bufsel(P.id, cur, s);
+    float* Xo = bufsel(P.x, nxt, s);
+    float* VXo = bufsel(P.vx, nxt, s);
+    float* VYo = bufsel(P.vy, nxt, s);
+    float* VZo = bufsel(P.vz, nxt, s);
+    uint32_t* IDo = bufsel(P.id, nxt, s);
+    if (!P.sort_cells[s]) {
+        // order-keeping compaction: this range's alive particles go, in order, to
+        // [cursor[2 nc + b], ...)
+        unsigned pos = cursor[2 * nc + blockIdx.x];
+        for (int64_t vb = begin; vb < end; vb += nt) {
+            const int64_t v = vb + tid;
+            const float x = v < end ? X[v] : -1.0f;
+            const bool alive = x > 0.0f;
+            const unsigned long long m = __ballot(alive);
+            if (lane == 0) wcnt[wid] = (unsigned)__popcll(m);
+            __syncthreads();
+            unsigned off = 0, tot = 0;
+            for (int w = 0; w < nw; ++w) {
+                const unsigned c = wcnt[w];
+                off += w < wid ? c : 0u;
+                tot += c;
+            }
+            __syncthreads();
+            if (alive) {
+                const unsigned d = pos + off + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+                Xo[d] = x;
+                VXo[d] = VX[v];
+                VYo[d] = VY[v];
+                VZo[d] = VZ[v];
+                IDo[d] = ID[v];
+            }
+            pos += tot;
         }
-    }
-    __syncthreads();
-    for (int i = tid; i < 2 * nc; i += nt) {
-        const unsigned c = h[i];
-        base[i] = c ? atomicAdd(&cursor[i], c) : 0u;
-        h[i] = 0;
-    }
-    __syncthreads();
-    for (int64_t v = begin + tid; v < end; v += nt) {
-        const int s = v >= ns0;
-        const int64_t i = s ? v - ns0 : v;
-        const float x = P.x[cur][s][i];
-        if (x > 0.0f) {
-            int j;
-            float w;
-            cell_of(x, nc, j, w);
-            const unsigned pos = base[s * nc + j] + atomicAdd(&h[s * nc + j], 1u);
-            P.x[nxt][s][pos] = x;
-            P.vx[nxt][s][pos] = P.vx[cur][s][i];
-            P.vy[nxt][s][pos] = P.vy[cur][s][i];
-            P.vz[nxt][s][pos] = P.vz[cur][s][i];
-            P.id[nxt][s][pos] = P.id[cur][s][i];
+    } else {
+        // cell sort: this block reserves, per cell, room after the blocks before it
+        for (int i = tid; i < nc; i += nt) h[i] = 0;
+        __syncthreads();
+        for (int64_t v = begin + tid; v < end; v += nt) {
+            const float x = X[v];
+            if (x > 0.0f) {
+                int j;
+                float w;
+                cell_of(x, nc, j, w);
+                atomicAdd(&h[j], 1u);
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < nc; i += nt) {
+            const unsigned c = h[i];
+            base[i] = c ? atomicAdd(&cursor[s * nc + i], c) : 0u;
+            h[i] = 0;
+        }
+        __syncthreads();
+        for (int64_t v = begin + tid; v < end; v += nt) {
+            const float x = X[v];
+            if (x > 0.0f) {
+                int j;
+                float w;
+                cell_of(x, nc, j, w);
+                const unsigned d = base[j] + atomicAdd(&h[j], 1u);
+                Xo[d] = x;
+                VXo[d] = VX[v];
+                VYo[d] = VY[v];
+                VZo[d] = VZ[v];
+                IDo[d] = ID[v];
+            }
         }
     }
     wait_memory_complete();
@@ -1273,14 +1369,15 @@ hipError_t launch_load(const Params& P, int s, int64_t n, double vth, hipStream_
 }
 
 hipError_t launch_sort(const Params& P, unsigned* cnt, unsigned* cursor, int blocks, int threads, hipStream_t st) {
-    const size_t lds_count = (size_t)2 * P.n_cells * sizeof(unsigned);
+    if (blocks < 2 || blocks > kMaxSortBlocks || threads != 1024) return hipErrorInvalidValue;
+    const size_t lds_count = (size_t)(P.n_cells + 1) * sizeof(unsigned);
     hipLaunchKernelGGL(sort_count_kernel, dim3(blocks), dim3(threads), lds_count, st, P, cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(1024), 0, st, P, cnt, cursor);
+    hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(1024), 0, st, P, cnt, cursor, blocks);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds_scatter = (size_t)4 * P.n_cells * sizeof(unsigned) + 16;
+    const size_t lds_scatter = (size_t)2 * P.n_cells * sizeof(unsigned) + 17 * sizeof(unsigned);
     hipLaunchKernelGGL(sort_scatter_kernel, dim3(blocks), dim3(threads), lds_scatter, st, P, cursor);
     return hipGetLastError();
 }

@@ -13,6 +13,7 @@ constexpr int kMaxProc = 16;
 constexpr int kMaxProcPerSpecies = 8;
 constexpr int kMaxCells = 4096;
 constexpr int kBirthSortCap = 2048;   // births per step ranked in LDS; more take a slow path
+constexpr int kMaxSortBlocks = 4096;  // workgroups of the periodic reordering
 // Charge deposit in fixed point: a particle's two cloud-in-cell weights are integers
 // summing to 2^24, accumulated with integer atomics, so the node charges are exact and
 // independent of the order of accumulation (bitwise reproducible runs).
@@ -114,6 +115,7 @@ struct Params {
     int32_t moments_every;
     int32_t steps_per_period;
     int32_t pad0;
+    int32_t sort_cells[2];    // periodic reordering per species: 1 cell sort, 0 compaction only
     float ncf;           // n_cells as float: the grounded electrode in cell units
     float dt_over_dx;    // drift factor for positions in cell units
     float dt;

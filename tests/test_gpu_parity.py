@@ -219,13 +219,14 @@ def test_gauss_law_and_charge_bookkeeping():
 
 
 def test_sort_does_not_change_results():
-    """The cell sort only permutes storage: with the exact fixed-point deposit, runs with and
-    without sorting are bitwise equal per id."""
+    """The periodic reordering only permutes storage: with the exact fixed-point deposit,
+    runs without it, with electrons sorted by cell and with electrons only compacted are
+    bitwise equal per id."""
     base = W.small_argon(seed=2)
     log("sort invariance")
     out = []
-    for se in (0, 1, 7):
-        with B.Discharge(base.replace(sort_every=se)) as d:
+    for se, eo in ((0, -1), (1, 1), (7, 1), (1, 0), (7, 0)):
+        with B.Discharge(base.replace(sort_every=se, electron_order=eo)) as d:
             d.step(50)
             out.append([d.particles(s) for s in (0, 1)] + [d.counters()])
     for r in out[1:]:
@@ -236,4 +237,5 @@ def test_sort_does_not_change_results():
             for key in ("x", "vx", "vy", "vz"):
                 assert np.array_equal(a[key][ka], b[key][kb]), (s, key)
         assert r[2]["n_alive"] == out[0][2]["n_alive"]
-    assert out[1][2]["n_slots"] == out[1][2]["n_alive"]   # compacted after the last sort
+    for k in (1, 3):   # compacted after the last reordering (every step)
+        assert out[k][2]["n_slots"] == out[k][2]["n_alive"]

@@ -75,6 +75,7 @@ class Discharge:
     sort_every: int = 20
     moments_every: int = 1
     max_births_per_step: int = 65536
+    electron_order: int = -1   # periodic electron reordering: 1 by cell, 0 compaction only, -1 automatic
 
     @property
     def steps_per_period(self) -> int:
