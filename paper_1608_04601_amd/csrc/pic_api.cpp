@@ -20,6 +20,7 @@ hipError_t launch_load(const Params& P, int s, int64_t n, double vth, hipStream_
 hipError_t launch_sort(const Params& P, unsigned* cnt, unsigned* cursor, int blocks, int threads, hipStream_t st);
 hipError_t launch_reset_window(const Params& P, hipStream_t st);
 hipError_t set_pass_lds_limit(size_t bytes);
+hipError_t pass_occupancy(int threads, size_t lds, int* blocks_per_cu);
 }  // namespace pic
 
 namespace {
@@ -480,15 +481,25 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
                                std::max((size_t)8 * nn, (size_t)pic::kBirthSortCap * 8);
         h->lds = std::max(pass_lds, epi_lds);
         const int64_t total = c.n_init_super[0] + c.n_init_super[1];
-        if (c.launch_blocks > 0) {
-            h->blocks = c.launch_blocks;
-        } else {
-            const int64_t per_block = (int64_t)h->threads * 8;
-            h->blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (total + per_block - 1) / per_block));
-        }
         h->sort_threads = 1024;
         h->sort_blocks = (int)std::min<int64_t>(pic::kMaxSortBlocks, std::max<int64_t>(2, (total + 8191) / 8192));
         if (!hip_ok(h, pic::set_pass_lds_limit(h->lds), "hipFuncSetAttribute")) goto fail_init;
+        if (c.launch_blocks > 0) {
+            h->blocks = c.launch_blocks;
+        } else {
+            // Workgroups resident at once (LDS and registers permitting) on all compute
+            // units; at most two such rounds (the second evens out the uneven finish of
+            // the first), and at least 8 particles per thread.
+            int cus = 0, per_cu = 0;
+            if (!hip_ok(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device),
+                        "hipDeviceGetAttribute") ||
+                !hip_ok(h, pic::pass_occupancy(h->threads, h->lds, &per_cu), "occupancy"))
+                goto fail_init;
+            const int64_t resident = std::max<int64_t>(1, (int64_t)cus * std::max(per_cu, 1));
+            const int64_t per_block = (int64_t)h->threads * 8;
+            const int64_t want = std::max<int64_t>(1, (total + per_block - 1) / per_block);
+            h->blocks = (int)(want >= 2 * resident ? 2 * resident : std::min(want, resident));
+        }
 
         if (!hip_ok(h, hipMemcpyAsync(tab, htab.data(), htab.size() * sizeof(float), hipMemcpyHostToDevice, h->stream),
                     "upload tables") ||

@@ -1387,6 +1387,10 @@ hipError_t launch_reset_window(const Params& P, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t pass_occupancy(int threads, size_t lds, int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pass_kernel<kComplete | kAdvance>, threads, lds);
+}
+
 hipError_t set_pass_lds_limit(size_t bytes) {
     const int b = (int)bytes;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete | kAdvance>),
