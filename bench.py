@@ -33,8 +33,10 @@ def kernel_source_sha():
 
 
 def stored_traffic(workload_name):
-    """HBM bytes per launch of the particle pass from the committed rocprofv3 counter summary,
-    or None when the summary is absent or was taken on a different kernel source."""
+    """HBM bytes per particle-step of the particle pass from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a plain device copy of
+    known size), or None when the summary is absent or was taken on a different kernel
+    source."""
     path = os.path.join(ROOT, "profiles", f"pass_kernel_{workload_name}_counters.txt")
     if not os.path.exists(path):
         return None
@@ -47,7 +49,7 @@ def stored_traffic(workload_name):
     if vals.get("kernel_source_sha") != kernel_source_sha():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_particle_step"])
     except (KeyError, ValueError):
         return None
 
@@ -75,7 +77,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="production", choices=sorted(workloads_by_name()))
-    ap.add_argument("--cpu-steps", type=int, default=20, help="oracle steps of the CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps of the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-blocks", type=int, default=0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -128,7 +130,8 @@ def main():
         c3 = d.counters()
         units = (c3["particle_steps"] - c2["particle_steps"]) / max(k_steps, 1)
         achieved = BYTES_PER_PARTICLE_STEP * units / (kern_ms * 1e-3) / 1e9
-        traffic = stored_traffic(args.workload)
+        bpps = stored_traffic(args.workload)
+        traffic = None if bpps is None else bpps * units   # bytes per launch at this launch's size
     finally:
         d.close()
 
@@ -168,6 +171,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_unit": "B per launch",
+            "traffic_GBs": None if traffic is None else traffic / (kern_ms * 1e-3) / 1e9,
             "kernel": "pass_kernel (fused complete+advance)",
             "kernel_ms_mean": kern_ms,
             "launches_timed": n_launch,
