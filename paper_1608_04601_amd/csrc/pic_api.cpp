@@ -399,7 +399,8 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         for (const pic_xsec& p : h->xs) ntab += (size_t)p.n_points;
         float* tab = nullptr;
         float* nullbound = nullptr;
-        if (!dev_alloc(h, &P.ctrl, 1) || !dev_alloc(h, &P.E, nn) || !dev_alloc(h, &P.Qs, (size_t)2 * nn) ||
+        if (!dev_alloc(h, &P.ctrl, 1) || !dev_alloc(h, &P.rep, (size_t)pic::kRepSets * pic::kRepStride) ||
+            !dev_alloc(h, &P.E, nn) || !dev_alloc(h, &P.Qs, (size_t)2 * nn) ||
             !dev_alloc(h, &nullbound, (size_t)pic::kNullBins + 1) ||
             !dev_alloc(h, &P.Q_last, nn) || !dev_alloc(h, &P.phi, nn) || !dev_alloc(h, &P.mom, (size_t)5 * nn) ||
             !dev_alloc(h, &P.birth_parent, (size_t)c.max_births_per_step) || !dev_alloc(h, &tab, std::max<size_t>(ntab, 1)) ||
@@ -488,8 +489,8 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
             h->blocks = c.launch_blocks;
         } else {
             // Workgroups resident at once (LDS and registers permitting) on all compute
-            // units; at most two such rounds (the second evens out the uneven finish of
-            // the first), and at least 8 particles per thread.
+            // units, and at least 8 particles per thread.  The device splits them between
+            // the species by measured cost, so one round is enough.
             int cus = 0, per_cu = 0;
             if (!hip_ok(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device),
                         "hipDeviceGetAttribute") ||
@@ -498,7 +499,7 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
             const int64_t resident = std::max<int64_t>(1, (int64_t)cus * std::max(per_cu, 1));
             const int64_t per_block = (int64_t)h->threads * 8;
             const int64_t want = std::max<int64_t>(1, (total + per_block - 1) / per_block);
-            h->blocks = (int)(want >= 2 * resident ? 2 * resident : std::min(want, resident));
+            h->blocks = (int)std::min(want, resident);
         }
 
         if (!hip_ok(h, hipMemcpyAsync(tab, htab.data(), htab.size() * sizeof(float), hipMemcpyHostToDevice, h->stream),
@@ -514,8 +515,11 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
             c0.next_id[s] = c.n_init_super[s];
         }
         c0.period_valid = 1;
+        c0.cost_ratio = 1.0;
         if (!hip_ok(h, hipMemcpyAsync(P.ctrl, &c0, sizeof(c0), hipMemcpyHostToDevice, h->stream), "upload ctrl") ||
             !hip_ok(h, hipMemsetAsync(P.Qs, 0, 2 * nn * sizeof(unsigned long long), h->stream), "zero Q") ||
+            !hip_ok(h, hipMemsetAsync(P.rep, 0, pic::kRepSets * pic::kRepStride * sizeof(unsigned long long), h->stream),
+                    "zero counter sets") ||
             !hip_ok(h, hipMemsetAsync(P.mom, 0, 5 * nn * sizeof(double), h->stream), "zero moments") ||
             !hip_ok(h, hipMemsetAsync(h->sort_cnt, 0, (2 * nc + pic::kMaxSortBlocks) * sizeof(unsigned), h->stream),
                     "zero sort counts"))

@@ -32,7 +32,8 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
                                         uint32_t k0, uint32_t k1) {
     // The round keys are recomputed at every call (scalar adds) rather than kept live in
     // scalar registers across the particle loop, where registers are scarce.
-    asm volatile("" : "+s"(k0), "+s"(k1));
+    k0 = __builtin_amdgcn_readfirstlane(k0);
+    k1 = __builtin_amdgcn_readfirstlane(k1);
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
@@ -118,7 +119,11 @@ __device__ __forceinline__ void wait_memory_complete() {
 }
 
 // LDS counter slots of one workgroup
-enum : int { kCntAbs = 0, kCntColl = 4, kCntViol = 20, kCntErr = 22, kCntLast = 31, kCntSlots = 32 };
+enum : int { kCntAbs = 0, kCntColl = 4, kCntViol = 20, kCntErr = 22, kCntTicks = 23, kCntParts = 25, kCntLast = 31,
+             kCntSlots = 32 };
+static_assert(kCntAbs == kRepAbs && kCntColl == kRepColl && kCntViol == kRepViol && kCntErr == kRepErr &&
+                  kCntTicks == kRepTicks && kCntParts == kRepParts,
+              "LDS counter slots and report words line up");
 
 // LDS of one workgroup of the particle pass.  A workgroup handles one species at a time:
 // Q holds that species' deposit and M its second moment quantity (electron energy or ion
@@ -890,6 +895,22 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
     }
     __syncthreads();
 
+    // ---- the workgroups' counters, summed over the sets (which are cleared for the next launch)
+    if (tid < kRepDone) {
+        unsigned long long v = 0;
+        for (int q = 0; q < kRepSets; ++q) {
+            const unsigned long long x = ld_agent(&P.rep[q * kRepStride + tid]);
+            v = (tid == kRepErr) ? (v | x) : (v + x);
+        }
+        if (tid < kRepColl) cs->absorbed_step[(tid - kRepAbs) >> 1][(tid - kRepAbs) & 1] += v;
+        else if (tid < kRepViol) cs->coll[tid - kRepColl] += v;
+        else if (tid < kRepErr) cs->viol[tid - kRepViol] += v;
+        else if (tid == kRepErr) atomicOr(&cs->err, (unsigned)v);
+        else if (tid < kRepParts) cs->cost_ticks[tid - kRepTicks] = v;
+        else cs->cost_parts[tid - kRepParts] = v;
+    }
+    __syncthreads();
+    for (int w = tid; w < kRepSets * kRepStride; w += nt) P.rep[w] = 0ull;
     // ---- completion of the previous step: births
     if (MODE & kComplete) {
         const unsigned nb = cs->n_births;
@@ -968,7 +989,18 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
             cs->sigmad = -P.eps0 * EN;
         }
     }
-    if (tid == 0) cs->done = 0;
+    if (tid == 0) {
+        cs->done = 0;
+        if ((MODE & kAdvance) && cs->cost_parts[0] > 0 && cs->cost_parts[1] > 0 && cs->cost_ticks[1] > 0) {
+            const double r = ((double)cs->cost_ticks[0] / (double)cs->cost_parts[0]) /
+                             ((double)cs->cost_ticks[1] / (double)cs->cost_parts[1]);
+            cs->cost_ratio = fmin(4.0, fmax(0.25, 0.8 * cs->cost_ratio + 0.2 * r));
+        }
+        for (int q = 0; q < 2; ++q) {
+            cs->cost_ticks[q] = 0;
+            cs->cost_parts[q] = 0;
+        }
+    }
     __syncthreads();
     for (int w = tid; w < kWords; w += nt) gw[w] = cw[w];
 }
@@ -1003,15 +1035,16 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
         for (int i = tid; i <= kNullBins; i += nt) L.U[i] = P.nullbound[i];
 
     // Workgroups are species-pure: the first G_e take the electrons, the rest the ions, in
-    // proportion to the slot counts (a single workgroup takes both, one after the other).
+    // proportion to the expected work, slot counts weighted by the measured cost per slot of
+    // each species (a single workgroup takes both, one after the other).
     const int G = gridDim.x;
     int64_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
     if (G == 1) {
         e0 = ns0;
         e1 = ns1;
     } else {
-        const int64_t total = ns0 + ns1;
-        int Ge = total > 0 ? (int)(((double)G * (double)ns0) / (double)total + 0.5) : G / 2;
+        const double w0 = (double)ns0 * C->cost_ratio, w1 = (double)ns1;
+        int Ge = (w0 + w1) > 0.0 ? (int)((double)G * w0 / (w0 + w1) + 0.5) : G / 2;
         if (ns0 > 0) Ge = max(Ge, 1);
         if (ns1 > 0) Ge = min(Ge, G - 1);
         if (ns1 == 0) Ge = G;
@@ -1030,6 +1063,7 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     for (int s = 0; s < 2; ++s) {
         const int64_t b = s ? b1 : b0, e = s ? e1 : e0;
         if (!(e > b)) continue;
+        const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
         for (int i = tid; i < nn; i += nt) {
             L.Q[i] = 0ull;
             if (sample) L.M[i] = 0ull;
@@ -1040,6 +1074,10 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
         else
             run_range<MODE, 1>(P, L, b, e, stepf, cur, ns0, ns1, sample);
         __syncthreads();
+        if (tid == 0 && (MODE & kAdvance)) {   // balance data for the next launch's split
+            L.cnt[kCntTicks + s] = (uint32_t)(__builtin_amdgcn_s_memrealtime() - t0);
+            L.cnt[kCntParts + s] = (uint32_t)(e - b);
+        }
         // this species' deposit, and its energy (e) or v_x (i) sums
         unsigned long long* qg = P.Qs + s * nn;
         double* sec = P.mom + (s ? 3 * nn : 2 * nn);
@@ -1054,20 +1092,26 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
         }
         __syncthreads();
     }
-    if (tid < 4) {
-        if (L.cnt[kCntAbs + tid]) atomicAdd(&C->absorbed_step[tid >> 1][tid & 1], (unsigned long long)L.cnt[kCntAbs + tid]);
-    } else if (tid < 4 + kMaxProc) {
-        if (L.cnt[tid]) atomicAdd(&C->coll[tid - kCntColl], (unsigned long long)L.cnt[tid]);
-    } else if (tid < kCntErr) {
-        if (L.cnt[tid]) atomicAdd(&C->viol[tid - kCntViol], (unsigned long long)L.cnt[tid]);
+    // this workgroup's counters to its set (LDS slot k maps to set word k, see kRep*)
+    const int set = blockIdx.x % kRepSets;
+    unsigned long long* rs = P.rep + set * kRepStride;
+    if (tid < kCntErr) {
+        if (L.cnt[tid]) atomicAdd(&rs[tid], (unsigned long long)L.cnt[tid]);
     } else if (tid == kCntErr) {
-        if (L.cnt[tid]) atomicOr(&C->err, L.cnt[tid]);
+        if (L.cnt[tid]) atomicOr(&rs[kRepErr], (unsigned long long)L.cnt[tid]);
+    } else if (tid < kCntErr + 5) {   // ticks and slots of the species run
+        if (L.cnt[tid]) atomicAdd(&rs[tid], (unsigned long long)L.cnt[tid]);
     }
     wait_memory_complete();
     __syncthreads();
     if (tid == 0) {
-        const unsigned prev = atomicAdd(&C->done, 1u);
-        L.cnt[kCntLast] = (prev == gridDim.x - 1) ? 1u : 0u;
+        // two-level completion count: the last workgroup of its set counts the set
+        const int G = gridDim.x;
+        const unsigned members = (unsigned)((G - set + kRepSets - 1) / kRepSets);
+        const unsigned sets = (unsigned)min(G, kRepSets);
+        unsigned last = 0;
+        if (atomicAdd(&rs[kRepDone], 1ull) == members - 1) last = atomicAdd(&C->done, 1u) == sets - 1 ? 1u : 0u;
+        L.cnt[kCntLast] = last;
     }
     __syncthreads();
     if (!L.cnt[kCntLast]) return;

@@ -14,6 +14,13 @@ constexpr int kMaxProcPerSpecies = 8;
 constexpr int kMaxCells = 4096;
 constexpr int kBirthSortCap = 2048;   // births per step ranked in LDS; more take a slow path
 constexpr int kMaxSortBlocks = 4096;  // workgroups of the periodic reordering
+// Per-workgroup counters of the particle pass go to kRepSets sets (workgroup b to set
+// b % kRepSets), each on its own 256-byte stretch, so that their atomics do not all
+// serialise on the control block's few cache lines; the last workgroup sums the sets.
+constexpr int kRepSets = 16;
+constexpr int kRepStride = 32;        // 64-bit words per set
+enum : int { kRepAbs = 0, kRepColl = 4, kRepViol = 20, kRepErr = 22, kRepTicks = 23, kRepParts = 25,
+             kRepDone = 27 };
 // Charge deposit in fixed point: a particle's two cloud-in-cell weights are integers
 // summing to 2^24, accumulated with integer atomics, so the node charges are exact and
 // independent of the order of accumulation (bitwise reproducible runs).
@@ -73,6 +80,9 @@ struct Ctrl {
     int32_t period_valid;
     int32_t pad;
     unsigned long long sort_alive[2];  // alive count found by the sort histogram
+    unsigned long long cost_ticks[2];  // workgroup time spent per species in the running launch
+    unsigned long long cost_parts[2];  // and the slots it covered
+    double cost_ratio;                 // smoothed time per electron slot / time per ion slot
 };
 
 struct ProcDev {
@@ -97,6 +107,7 @@ struct Params {
     Ctrl* ctrl;
     float* E;            // node field, FP32 copy for the gather [nn]
     unsigned long long* Qs;  // node deposit per species, fixed point: 2^24 per particle [2][nn]
+    unsigned long long* rep; // per-workgroup counter sets [kRepSets][kRepStride]
     double* Q_last;      // charge of the last solve [C/m^2] [nn]
     double* phi;         // node potential [V] [nn]
     double* mom;         // moment window sums [5][nn]: dens_e, dens_i, energy_e, flux_i, phi
