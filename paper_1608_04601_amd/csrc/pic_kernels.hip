@@ -994,7 +994,7 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
         if ((MODE & kAdvance) && cs->cost_parts[0] > 0 && cs->cost_parts[1] > 0 && cs->cost_ticks[1] > 0) {
             const double r = ((double)cs->cost_ticks[0] / (double)cs->cost_parts[0]) /
                              ((double)cs->cost_ticks[1] / (double)cs->cost_parts[1]);
-            cs->cost_ratio = fmin(4.0, fmax(0.25, 0.8 * cs->cost_ratio + 0.2 * r));
+            cs->cost_ratio = fmin(4.0, fmax(0.25, 0.95 * cs->cost_ratio + 0.05 * r));
         }
         for (int q = 0; q < 2; ++q) {
             cs->cost_ticks[q] = 0;
