@@ -227,6 +227,39 @@ int pic_get_decisions(pic_handle* h, int species, uint32_t* id, int8_t* code, in
  * handle's stream.  *n_launches receives the number of timed launches. */
 int pic_timing(pic_handle* h, int start, double* mean_ms, int64_t* n_launches);
 
+/* ---- Batches of independent discharges (a parameter sweep, the paper's study design,
+ * Table "tab:discharge": several pressures and gases) advanced together: one particle-pass
+ * launch per step serves every discharge of the batch, each on its own share of the
+ * workgroups (in proportion to its particles) and with its own field solve.  Results are
+ * those of advancing each discharge alone (bitwise, per particle id). */
+typedef struct pic_batch pic_batch;
+
+/* Create n >= 1 discharges from cfgs[0..n-1] on one HIP stream (NULL = null stream).  All
+ * must fit one workgroup size: either every n_cells <= 2047 or every n_cells > 1024.
+ * launch_blocks of the configs is ignored for batched steps.  On error *out is NULL. */
+int pic_batch_init(const pic_config* cfgs, int n, void* hip_stream, pic_batch** out);
+
+/* Enqueue n steps of every discharge; returns without waiting.  Discharges left with
+ * different pending states by per-discharge calls are first brought to the same state. */
+int pic_batch_step(pic_batch* b, int64_t n_steps);
+
+/* Complete every discharge's pending step with one launch, synchronise, and report the
+ * first device error of any discharge. */
+int pic_batch_sync(pic_batch* b);
+
+/* Borrow the handle of discharge k (0 <= k < n) for the per-discharge calls (moments,
+ * counters, particles, fields); valid until pic_batch_free, which frees it.  Do not call
+ * pic_free or pic_step on it. */
+int pic_batch_handle(pic_batch* b, int k, pic_handle** h);
+
+/* Number of workgroups of discharge k in batched launches (for measurement). */
+int pic_batch_blocks(const pic_batch* b, int k, int* blocks);
+
+void pic_batch_free(pic_batch* b);
+
+/* Message for the last error of a batch (or of its creation when b is NULL). */
+const char* pic_batch_last_error(const pic_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,9 @@ MAX_PROCESSES = 16
 
 EXPORTED = ("pic_init", "pic_step", "pic_sync", "pic_moments", "pic_free", "pic_last_error",
             "pic_get_counters", "pic_get_derived", "pic_get_particles", "pic_set_particles",
-            "pic_get_fields", "pic_set_record_decisions", "pic_get_decisions", "pic_timing")
+            "pic_get_fields", "pic_set_record_decisions", "pic_get_decisions", "pic_timing",
+            "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
+            "pic_batch_free", "pic_batch_last_error")
 
 
 class PicError(RuntimeError):
@@ -106,6 +108,13 @@ def load_library(path: str = None):
         "pic_set_record_decisions": (C.c_int, [H, C.c_int]),
         "pic_get_decisions": (C.c_int, [H, C.c_int, u32p, C.POINTER(C.c_int8), C.c_int64, C.POINTER(C.c_int64)]),
         "pic_timing": (C.c_int, [H, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "pic_batch_init": (C.c_int, [C.POINTER(pic_config), C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+        "pic_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
+        "pic_batch_sync": (C.c_int, [C.c_void_p]),
+        "pic_batch_handle": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
+        "pic_batch_blocks": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+        "pic_batch_free": (None, [C.c_void_p]),
+        "pic_batch_last_error": (C.c_char_p, [C.c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -267,6 +276,93 @@ def torch_stream():
     """hipStream_t of torch's current stream on the current device (plumbing only)."""
     import torch
     return torch.cuda.current_stream().cuda_stream
+
+
+def _check_batch(b, rc):
+    if rc != PIC_OK:
+        msg = load_library().pic_batch_last_error(b)
+        raise PicError(rc, msg.decode() if msg else "")
+
+
+class Batch:
+    """Owning wrapper around a batch of discharges advanced by one launch per step; item k
+    is a non-owning per-discharge view (moments, counters, particles, fields)."""
+
+    def __init__(self, discs, stream=None):
+        L = load_library()
+        self.discs = list(discs)
+        self._configs = [Config(d) for d in self.discs]
+        arr = (pic_config * len(self._configs))(*[c.c for c in self._configs])
+        self._arr = arr
+        b = C.c_void_p()
+        _check_batch(None, L.pic_batch_init(arr, len(self._configs), C.c_void_p(stream) if stream else None,
+                                            C.byref(b)))
+        self.b = b
+        self.views = []
+        for k, d in enumerate(self.discs):
+            h = C.c_void_p()
+            _check_batch(self.b, L.pic_batch_handle(self.b, k, C.byref(h)))
+            self.views.append(_View(h, d))
+
+    def step(self, n):
+        _check_batch(self.b, load_library().pic_batch_step(self.b, int(n)))
+
+    def sync(self):
+        _check_batch(self.b, load_library().pic_batch_sync(self.b))
+
+    def blocks(self, k):
+        g = C.c_int()
+        _check_batch(self.b, load_library().pic_batch_blocks(self.b, k, C.byref(g)))
+        return g.value
+
+    def __len__(self):
+        return len(self.views)
+
+    def __getitem__(self, k):
+        return self.views[k]
+
+    def close(self):
+        if self.b:
+            load_library().pic_batch_free(self.b)
+            self.b = None
+            self.views = []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _View:
+    """Per-discharge calls on a handle owned elsewhere (a batch)."""
+
+    def __init__(self, h, disc):
+        self.h, self.disc, self.n_nodes = h, disc, disc.n_cells + 1
+
+    def sync(self):
+        pic_sync(self.h)
+
+    def moments(self, reset=False):
+        return pic_moments(self.h, self.n_nodes, reset)
+
+    def counters(self):
+        return pic_get_counters(self.h)
+
+    def derived(self):
+        return pic_get_derived(self.h)
+
+    def particles(self, species):
+        return pic_get_particles(self.h, species)
+
+    def fields(self):
+        return pic_get_fields(self.h, self.n_nodes)
 
 
 class Discharge:

@@ -21,6 +21,10 @@ hipError_t launch_sort(const Params& P, unsigned* cnt, unsigned* cursor, int blo
 hipError_t launch_reset_window(const Params& P, hipStream_t st);
 hipError_t set_pass_lds_limit(size_t bytes);
 hipError_t pass_occupancy(int threads, size_t lds, int* blocks_per_cu);
+hipError_t launch_pass_batch(int mode, const Params* batch, const int* seg, int nd, int blocks, int threads,
+                             size_t lds, hipStream_t st);
+hipError_t set_pass_batch_lds_limit(size_t bytes);
+hipError_t pass_batch_occupancy(int threads, size_t lds, int* blocks_per_cu);
 }  // namespace pic
 
 namespace {
@@ -90,6 +94,18 @@ bool hip_ok(pic_handle* h, hipError_t e, const char* what) {
     if (e == hipSuccess) return true;
     fail(h, PIC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
     return false;
+}
+
+// Dynamic LDS of the particle pass for nn nodes and nt threads: the larger of the
+// streaming layout (counters, fixed-point deposit, fixed-point moment sum, field,
+// null-collision bounds, candidate queues of 128 three-word entries per wave) and the
+// epilogue layout (control block copy, three FP64 node arrays, scratch, then the
+// potential or, before the solve, the birth keys and parents).
+size_t pass_lds_bytes(int nn, int nt) {
+    const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 8 + 4) + (size_t)(pic::kNullBins + 1) * 4 +
+                            (size_t)(nt / 64) * 128 * 3 * 4;
+    const size_t epi_lds = 512 + (size_t)24 * nn + 512 + std::max((size_t)8 * nn, (size_t)pic::kBirthSortCap * 8);
+    return std::max(pass_lds, epi_lds);
 }
 
 // sigma_j at frame energy eps (FP64): zero below threshold, floor emin, clamp at the
@@ -472,15 +488,7 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         // field, the private deposit and moment grids, the null-collision bounds and the
         // candidate queue
         h->threads = nn <= 1025 ? 256 : 1024;
-        // counters, fixed-point deposit, fixed-point moment sum, field, bounds, candidate
-        // queues (128 entries of three words per wave)
-        const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 8 + 4) + (size_t)(pic::kNullBins + 1) * 4 +
-                                (size_t)(h->threads / 64) * 128 * 3 * 4;
-        // last workgroup: control block copy, three FP64 node arrays, scratch, then the
-        // potential or (before the solve) the birth keys and parents
-        const size_t epi_lds = 512 + (size_t)24 * nn + 512 +
-                               std::max((size_t)8 * nn, (size_t)pic::kBirthSortCap * 8);
-        h->lds = std::max(pass_lds, epi_lds);
+        h->lds = pass_lds_bytes(nn, h->threads);
         const int64_t total = c.n_init_super[0] + c.n_init_super[1];
         h->sort_threads = 1024;
         h->sort_blocks = (int)std::min<int64_t>(pic::kMaxSortBlocks, std::max<int64_t>(2, (total + 8191) / 8192));
@@ -818,6 +826,191 @@ int pic_timing(pic_handle* h, int start, double* mean_ms, int64_t* n_launches) {
     if (n_launches) *n_launches = h->n_timed;
     h->timing = false;
     return PIC_OK;
+}
+
+
+// ---------------------------------------------------------------------------------------
+// Batches of discharges
+// ---------------------------------------------------------------------------------------
+struct pic_batch {
+    std::vector<pic_handle*> hs;
+    hipStream_t stream = nullptr;
+    pic::Params* dparams = nullptr;
+    int* dseg = nullptr;
+    std::vector<int> seg;   // workgroup offsets, n + 1 entries
+    int threads = 256;
+    size_t lds = 0;
+    int status = PIC_OK;
+    std::string err;
+};
+
+namespace {
+thread_local std::string g_batch_error;
+
+int bfail(pic_batch* b, int code, const std::string& msg) {
+    if (!b) {
+        g_batch_error = msg;
+        return code;
+    }
+    if (b->status == PIC_OK) {
+        b->status = code;
+        b->err = msg;
+    }
+    return b->status;
+}
+
+// first error of any discharge, with its index
+int batch_status(pic_batch* b) {
+    if (b->status) return b->status;
+    for (size_t k = 0; k < b->hs.size(); ++k)
+        if (b->hs[k]->status)
+            return bfail(b, b->hs[k]->status, "discharge " + std::to_string(k) + ": " + b->hs[k]->err);
+    return PIC_OK;
+}
+
+// Brings every discharge to the same pending state: completes, one by one, the pending
+// steps of a batch whose discharges disagree (per-discharge queries complete theirs).
+int batch_align(pic_batch* b) {
+    bool any = false, all = true;
+    for (pic_handle* h : b->hs) {
+        any |= h->pending;
+        all &= h->pending;
+    }
+    if (any && !all)
+        for (pic_handle* h : b->hs)
+            if (h->pending && complete_pending(h)) break;
+    return batch_status(b);
+}
+
+int batch_launch(pic_batch* b, int mode) {
+    const hipError_t e = pic::launch_pass_batch(mode, b->dparams, b->dseg, (int)b->hs.size(), b->seg.back(),
+                                                b->threads, b->lds, b->stream);
+    if (e != hipSuccess) return bfail(b, PIC_EHIP, std::string("batched pass launch: ") + hipGetErrorString(e));
+    return PIC_OK;
+}
+}  // namespace
+
+void pic_batch_free(pic_batch* b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    for (pic_handle* h : b->hs) pic_free(h);
+    if (b->dparams) (void)hipFree(b->dparams);
+    if (b->dseg) (void)hipFree(b->dseg);
+    delete b;
+}
+
+int pic_batch_init(const pic_config* cfgs, int n, void* hip_stream, pic_batch** out) {
+    if (!out) return bfail(nullptr, PIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfgs) return bfail(nullptr, PIC_EINVAL, "cfgs is NULL");
+    if (n < 1 || n > 4096) return bfail(nullptr, PIC_EINVAL, "n must be in [1, 4096]");
+    for (int k = 0; k < n; ++k) {   // every configuration is checked before any device work
+        const std::string bad = validate(&cfgs[k]);
+        if (!bad.empty()) return bfail(nullptr, PIC_EINVAL, "discharge " + std::to_string(k) + ": " + bad);
+    }
+    pic_batch* b = new (std::nothrow) pic_batch();
+    if (!b) return bfail(nullptr, PIC_ENOMEM, "out of host memory");
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    int max_nn = 0;
+    for (int k = 0; k < n; ++k) {
+        pic_handle* h = nullptr;
+        const int rc = pic_init(&cfgs[k], hip_stream, &h);
+        if (rc) {
+            const std::string msg = "discharge " + std::to_string(k) + ": " + g_init_error;
+            pic_batch_free(b);
+            return bfail(nullptr, rc, msg);
+        }
+        b->hs.push_back(h);
+        max_nn = std::max(max_nn, cfgs[k].n_cells + 1);
+    }
+    // one workgroup size for the launch: the epilogue needs n_cells + 1 <= 8 x blockDim
+    b->threads = max_nn <= 2048 ? 256 : 1024;
+    for (int k = 0; k < n; ++k) b->lds = std::max(b->lds, pass_lds_bytes(cfgs[k].n_cells + 1, b->threads));
+    hipError_t e = pic::set_pass_batch_lds_limit(b->lds);
+    int cus = 0, per_cu = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->hs[0]->device);
+    if (e == hipSuccess) e = pic::pass_batch_occupancy(b->threads, b->lds, &per_cu);
+    if (e != hipSuccess) {
+        const std::string msg = std::string("batch set-up: ") + hipGetErrorString(e);
+        pic_batch_free(b);
+        return bfail(nullptr, PIC_EHIP, msg);
+    }
+    // workgroups in proportion to the particles, about one resident round in all; each
+    // discharge has at least 2 and at most one per 4 x blockDim particles
+    double total = 0.0;
+    for (int k = 0; k < n; ++k) total += (double)(cfgs[k].n_init_super[0] + cfgs[k].n_init_super[1]);
+    const double resident = (double)std::max(1, cus * std::max(per_cu, 1));
+    b->seg.assign(1, 0);
+    for (int k = 0; k < n; ++k) {
+        const double nk = (double)(cfgs[k].n_init_super[0] + cfgs[k].n_init_super[1]);
+        const int cap = std::max(2, (int)std::ceil(nk / (4.0 * b->threads)));
+        const int g = std::min(cap, std::max(2, (int)std::lround(resident * nk / std::max(total, 1.0))));
+        b->seg.push_back(b->seg.back() + g);
+    }
+    std::vector<pic::Params> hp(n);
+    for (int k = 0; k < n; ++k) hp[k] = b->hs[k]->P;
+    if ((e = hipMalloc(&b->dparams, sizeof(pic::Params) * n)) != hipSuccess ||
+        (e = hipMalloc(&b->dseg, sizeof(int) * (n + 1))) != hipSuccess ||
+        (e = hipMemcpy(b->dparams, hp.data(), sizeof(pic::Params) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b->dseg, b->seg.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess) {
+        const std::string msg = std::string("batch set-up: ") + hipGetErrorString(e);
+        pic_batch_free(b);
+        return bfail(nullptr, e == hipErrorOutOfMemory ? PIC_ENOMEM : PIC_EHIP, msg);
+    }
+    *out = b;
+    return PIC_OK;
+}
+
+int pic_batch_step(pic_batch* b, int64_t n_steps) {
+    if (!b) return PIC_EINVAL;
+    if (batch_status(b)) return b->status;
+    if (n_steps < 0) return bfail(b, PIC_EINVAL, "n_steps must be >= 0");
+    if (n_steps > 0 && batch_align(b)) return b->status;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const int mode = pic::kAdvance | (b->hs[0]->pending ? pic::kComplete : 0);
+        if (batch_launch(b, mode)) return b->status;
+        for (pic_handle* h : b->hs) {
+            h->pending = true;
+            if (h->cfg.sort_every > 0 && ++h->since_sort >= h->cfg.sort_every) {
+                if (!hip_ok(h, pic::launch_sort(h->P, h->sort_cnt, h->sort_cursor, h->sort_blocks, h->sort_threads,
+                                                h->stream),
+                            "sort launch"))
+                    return batch_status(b);
+                h->since_sort = 0;
+            }
+        }
+    }
+    return PIC_OK;
+}
+
+int pic_batch_sync(pic_batch* b) {
+    if (!b) return PIC_EINVAL;
+    if (batch_status(b)) return b->status;
+    if (batch_align(b)) return b->status;
+    if (b->hs[0]->pending) {
+        if (batch_launch(b, pic::kComplete)) return b->status;
+        for (pic_handle* h : b->hs) h->pending = false;
+    }
+    for (pic_handle* h : b->hs) check_device(h);
+    return batch_status(b);
+}
+
+int pic_batch_handle(pic_batch* b, int k, pic_handle** h) {
+    if (!b || !h) return PIC_EINVAL;
+    if (k < 0 || k >= (int)b->hs.size()) return bfail(b, PIC_EINVAL, "k out of range");
+    *h = b->hs[k];
+    return PIC_OK;
+}
+
+int pic_batch_blocks(const pic_batch* b, int k, int* blocks) {
+    if (!b || !blocks || k < 0 || k >= (int)b->hs.size()) return PIC_EINVAL;
+    *blocks = b->seg[k + 1] - b->seg[k];
+    return PIC_OK;
+}
+
+const char* pic_batch_last_error(const pic_batch* b) {
+    if (!b) return g_batch_error.c_str();
+    return b->err.c_str();
 }
 
 }  // extern "C"

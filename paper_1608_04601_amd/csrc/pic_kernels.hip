@@ -1005,9 +1005,9 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
     for (int w = tid; w < kWords; w += nt) gw[w] = cw[w];
 }
 
+// One launch's work of workgroup wg of the G workgroups that serve discharge P.
 template <int MODE>
-__global__ void __launch_bounds__(1024) pass_kernel(Params P) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void pass_body(const Params& P, unsigned char* smem, const int wg, const int G) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int nn = P.n_cells + 1;
     Ctrl* C = P.ctrl;
@@ -1037,7 +1037,6 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     // Workgroups are species-pure: the first G_e take the electrons, the rest the ions, in
     // proportion to the expected work, slot counts weighted by the measured cost per slot of
     // each species (a single workgroup takes both, one after the other).
-    const int G = gridDim.x;
     int64_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
     if (G == 1) {
         e0 = ns0;
@@ -1048,7 +1047,7 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
         if (ns0 > 0) Ge = max(Ge, 1);
         if (ns1 > 0) Ge = min(Ge, G - 1);
         if (ns1 == 0) Ge = G;
-        const int b = blockIdx.x;
+        const int b = wg;
         if (b < Ge) {
             const int64_t per = (ns0 + Ge - 1) / Ge;
             b0 = min((int64_t)b * per, ns0);
@@ -1093,7 +1092,7 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
         __syncthreads();
     }
     // this workgroup's counters to its set (LDS slot k maps to set word k, see kRep*)
-    const int set = blockIdx.x % kRepSets;
+    const int set = wg % kRepSets;
     unsigned long long* rs = P.rep + set * kRepStride;
     if (tid < kCntErr) {
         if (L.cnt[tid]) atomicAdd(&rs[tid], (unsigned long long)L.cnt[tid]);
@@ -1106,7 +1105,6 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     __syncthreads();
     if (tid == 0) {
         // two-level completion count: the last workgroup of its set counts the set
-        const int G = gridDim.x;
         const unsigned members = (unsigned)((G - set + kRepSets - 1) / kRepSets);
         const unsigned sets = (unsigned)min(G, kRepSets);
         unsigned last = 0;
@@ -1116,6 +1114,28 @@ __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     __syncthreads();
     if (!L.cnt[kCntLast]) return;
     epilogue<MODE>(P, smem, step, cur, ns0, ns1, sample);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(1024) pass_kernel(Params P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    pass_body<MODE>(P, smem, blockIdx.x, gridDim.x);
+}
+
+// Several independent discharges advanced by one launch: discharge d owns workgroups
+// [seg[d], seg[d+1]) and its parameters are batch[d]; each discharge's last workgroup runs
+// its own epilogue.  Every discharge takes the same step mode.
+template <int MODE>
+__global__ void __launch_bounds__(1024) pass_batch_kernel(const Params* __restrict__ batch,
+                                                          const int* __restrict__ seg, int nd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = blockIdx.x;
+    int lo = 0, hi = nd;   // seg[lo] <= b < seg[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg[mid] <= b) lo = mid; else hi = mid;
+    }
+    pass_body<MODE>(batch[lo], smem, b - seg[lo], seg[lo + 1] - seg[lo]);
 }
 
 // ----------------------------------------------------------------------------------
@@ -1402,6 +1422,43 @@ hipError_t launch_pass(int mode, const Params& P, int blocks, int threads, size_
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_pass_batch(int mode, const Params* batch, const int* seg, int nd, int blocks, int threads,
+                             size_t lds, hipStream_t st) {
+    switch (mode) {
+        case kComplete | kAdvance:
+            hipLaunchKernelGGL(pass_batch_kernel<kComplete | kAdvance>, dim3(blocks), dim3(threads), lds, st, batch, seg,
+                               nd);
+            break;
+        case kAdvance:
+            hipLaunchKernelGGL(pass_batch_kernel<kAdvance>, dim3(blocks), dim3(threads), lds, st, batch, seg, nd);
+            break;
+        case kComplete:
+            hipLaunchKernelGGL(pass_batch_kernel<kComplete>, dim3(blocks), dim3(threads), lds, st, batch, seg, nd);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t set_pass_batch_lds_limit(size_t bytes) {
+    const int b = (int)bytes;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_batch_kernel<kComplete | kAdvance>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_batch_kernel<kAdvance>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_batch_kernel<kComplete>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    return e;
+}
+
+hipError_t pass_batch_occupancy(int threads, size_t lds, int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pass_batch_kernel<kComplete | kAdvance>,
+                                                        threads, lds);
 }
 
 hipError_t launch_load(const Params& P, int s, int64_t n, double vth, hipStream_t st) {

@@ -102,3 +102,19 @@ def test_null_arguments():
     assert lib.pic_init(None, None, None) == B.PIC_EINVAL
     h = C.c_void_p()
     assert lib.pic_init(None, None, C.byref(h)) == B.PIC_EINVAL and not h
+
+
+def test_batch_null_and_invalid_arguments():
+    lib = B.load_library()
+    lib.pic_batch_free(None)  # NULL-safe
+    assert lib.pic_batch_step(None, 1) == B.PIC_EINVAL
+    assert lib.pic_batch_sync(None) == B.PIC_EINVAL
+    b = C.c_void_p()
+    assert lib.pic_batch_init(None, 1, None, C.byref(b)) == B.PIC_EINVAL and not b
+    cfg = B.Config(W.small_argon(n_super=100))
+    assert lib.pic_batch_init(C.byref(cfg.c), 0, None, C.byref(b)) == B.PIC_EINVAL and not b
+    assert b"n must be" in lib.pic_batch_last_error(None)
+    bad = B.Config(_bad(n_cells=1))
+    arr = (B.pic_config * 2)(cfg.c, bad.c)
+    assert lib.pic_batch_init(arr, 2, None, C.byref(b)) == B.PIC_EINVAL and not b
+    assert b"discharge 1" in lib.pic_batch_last_error(None)
