@@ -802,10 +802,40 @@ __device__ void bitonic_sort(uint32_t* keys, unsigned n2) {
     }
 }
 
+// In-place inclusive prefix sum of v[0..n) by one workgroup (blockDim a multiple of 64):
+// each thread sums a contiguous run, the run totals are scanned across the wave with
+// shuffles and across waves through part[blockDim / 64].
+__device__ void block_inclusive_scan(uint32_t* v, unsigned n, uint32_t* part) {
+    const unsigned tid = threadIdx.x, nt = blockDim.x, lane = tid & 63u, wv = tid >> 6;
+    const unsigned c = (n + nt - 1) / nt, b0 = min(tid * c, n), b1 = min(b0 + c, n);
+    uint32_t run = 0;
+    for (unsigned i = b0; i < b1; ++i) run += v[i];
+    uint32_t x = run;
+    for (unsigned d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) part[wv] = x;
+    __syncthreads();
+    uint32_t acc = x - run;
+    for (unsigned w = 0; w < wv; ++w) acc += part[w];
+    for (unsigned i = b0; i < b1; ++i) {
+        acc += v[i];
+        v[i] = acc;
+    }
+    __syncthreads();
+}
+
 // Ids of this launch's ionisation products: the k-th parent in ascending id order gives
-// next_id_e + k and next_id_i + k.  parents[] keeps the unsorted list.
-__device__ void assign_birth_ids(const Params& P, uint32_t* keys, uint32_t* parents, unsigned cur, int64_t ns0,
-                                 int64_t ns1, unsigned nbv, int64_t nid0, int64_t nid1) {
+// next_id_e + k and next_id_i + k (parents are distinct electrons).  Up to kBirthSortCap
+// parents are sorted in LDS and each finds its rank by binary search.  More are binned by
+// their leading id bits (a bin index that never decreases with the id): bin starts come
+// from a prefix sum of the bin counts, the parents are scattered to bin order in
+// P.birth_order, and a parent's rank is its bin's start plus the smaller ids in its bin,
+// so the work grows with the births times the mean bin occupancy.  keys and parents are
+// kBirthSortCap words each, contiguous; part holds blockDim / 64 words.
+__device__ void assign_birth_ids(const Params& P, uint32_t* keys, uint32_t* parents, uint32_t* part, unsigned cur,
+                                 int64_t ns0, int64_t ns1, unsigned nbv, int64_t nid0, int64_t nid1) {
     const int tid = threadIdx.x, nt = blockDim.x;
     if (nbv == 0) return;
     if (nbv <= (unsigned)kBirthSortCap) {
@@ -829,16 +859,39 @@ __device__ void assign_birth_ids(const Params& P, uint32_t* keys, uint32_t* pare
             bufsel(P.id, cur, 1)[ns1 + k] = (uint32_t)(nid1 + lo);
         }
         __syncthreads();
-    } else {
-        for (unsigned k = tid; k < nbv; k += nt) {
-            const uint32_t p = ld_agent(&P.birth_parent[k]);
-            unsigned rank = 0;
-            for (unsigned q = 0; q < nbv; ++q) rank += ld_agent(&P.birth_parent[q]) < p;
-            bufsel(P.id, cur, 0)[ns0 + k] = (uint32_t)(nid0 + rank);
-            bufsel(P.id, cur, 1)[ns1 + k] = (uint32_t)(nid1 + rank);
-        }
-        __syncthreads();
+        return;
     }
+    // bins 0..kBins-1 plus an end entry fill keys and parents
+    constexpr unsigned kBins = 2u * (unsigned)kBirthSortCap - 1u;
+    uint32_t* bin = keys;
+    // parent ids are below nid0 <= 2^32: keep their leading 12 bits
+    const unsigned bits = nid0 > 1 ? 64u - (unsigned)__clzll((unsigned long long)(nid0 - 1)) : 1u;
+    const unsigned sh = bits > 12u ? bits - 12u : 0u;
+    for (unsigned b = tid; b <= kBins; b += nt) bin[b] = 0u;
+    __syncthreads();
+    for (unsigned k = tid; k < nbv; k += nt) atomicAdd(&bin[min(ld_agent(&P.birth_parent[k]) >> sh, kBins - 1u)], 1u);
+    __syncthreads();
+    block_inclusive_scan(bin, kBins, part);   // bin[b] = end of bin b
+    if (tid == 0) bin[kBins] = nbv;
+    for (unsigned k = tid; k < nbv; k += nt) {
+        const uint32_t p = ld_agent(&P.birth_parent[k]);
+        const unsigned pos = atomicSub(&bin[min(p >> sh, kBins - 1u)], 1u) - 1u;
+        st_agent(&P.birth_order[pos], ((unsigned long long)p << 32) | k);
+    }
+    // now bin[b] = start of bin b and bin[b + 1] its end; the scattered entries are read
+    // back by other waves of this workgroup
+    __threadfence();
+    __syncthreads();
+    for (unsigned j = tid; j < nbv; j += nt) {
+        const unsigned long long e = ld_agent(&P.birth_order[j]);
+        const uint32_t p = (uint32_t)(e >> 32), k = (uint32_t)e;
+        const unsigned b = min(p >> sh, kBins - 1u), hi = bin[b + 1];
+        unsigned rank = bin[b];
+        for (unsigned q = bin[b]; q < hi; ++q) rank += (uint32_t)(ld_agent(&P.birth_order[q]) >> 32) < p;
+        bufsel(P.id, cur, 0)[ns0 + k] = (uint32_t)(nid0 + rank);
+        bufsel(P.id, cur, 1)[ns1 + k] = (uint32_t)(nid1 + rank);
+    }
+    __syncthreads();
 }
 
 // LDS layout of the epilogue (bytes): control block copy, then FP64 node arrays.
@@ -919,7 +972,7 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
         if ((int64_t)nbv > P.cap[0] - ns0) nbv = (unsigned)(P.cap[0] - ns0);
         if ((int64_t)nbv > P.cap[1] - ns1) nbv = (unsigned)(P.cap[1] - ns1);
         const int64_t nid0 = cs->next_id[0], nid1 = cs->next_id[1];
-        assign_birth_ids(P, keys, parents, cur, ns0, ns1, nbv, nid0, nid1);
+        assign_birth_ids(P, keys, parents, reinterpret_cast<uint32_t*>(scratch), cur, ns0, ns1, nbv, nid0, nid1);
         if (tid == 0) {
             if (nb > nbv) cs->err |= (nbv == (unsigned)P.max_births) ? kErrBirths : kErrCapacity;
             if (nid0 + nbv > 0x100000000ll || nid1 + nbv > 0x100000000ll) cs->err |= kErrIds;

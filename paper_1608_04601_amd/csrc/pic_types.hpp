@@ -12,7 +12,7 @@ namespace pic {
 constexpr int kMaxProc = 16;
 constexpr int kMaxProcPerSpecies = 8;
 constexpr int kMaxCells = 4096;
-constexpr int kBirthSortCap = 2048;   // births per step ranked in LDS; more take a slow path
+constexpr int kBirthSortCap = 2048;   // births per step ranked by a sort in LDS; more are binned
 constexpr int kMaxSortBlocks = 4096;  // workgroups of the periodic reordering
 // Per-workgroup counters of the particle pass go to kRepSets sets (workgroup b to set
 // b % kRepSets), each on its own 256-byte stretch, so that their atomics do not all
@@ -113,6 +113,7 @@ struct Params {
     double* mom;         // moment window sums [5][nn]: dens_e, dens_i, energy_e, flux_i, phi
     double mscale[2];    // fixed-point scale of the second moment quantity per species
     uint32_t* birth_parent;   // [max_births]
+    unsigned long long* birth_order;   // ranking scratch: (parent id << 32 | birth index) [max_births]
     int8_t* dec[2];      // decision record per slot, or null
     const float* tab;    // n_gas * sigma tables [1/m]
     const float* nullbound;   // [kNullBins + 1] electron collision-frequency bounds [1/s]
