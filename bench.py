@@ -23,7 +23,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 
 def workloads_by_name():
     import workloads as W
-    return {"production": W.production_helium, "large": W.large_argon, "small": W.small_argon}
+    return {"production": W.production_helium, "large": W.large_argon, "small": W.small_argon,
+            "sweep": W.sweep_argon}
 
 
 def kernel_source_sha():
@@ -32,12 +33,12 @@ def kernel_source_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic(workload_name):
+def stored_traffic(workload_name, kernel="pass_kernel"):
     """HBM bytes per particle-step of the particle pass from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a plain device copy of
     known size), or None when the summary is absent or was taken on a different kernel
     source."""
-    path = os.path.join(ROOT, "profiles", f"pass_kernel_{workload_name}_counters.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_name}_counters.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -71,6 +72,95 @@ def cpu_baseline(disc, steps):
                        f"({disc.n_super[0]}+{disc.n_super[1]} particles), 1 thread, {dt:.1f} s")
 
 
+def run_sweep(args, B, torch):
+    """The batched parameter sweep: every discharge of the sweep advanced by one launch per
+    step.  Also times the same discharges advanced one after the other (one launch each per
+    step) for comparison."""
+    discs = workloads_by_name()["sweep"]()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    bt = B.Batch(discs, stream=stream.cuda_stream)
+    try:
+        bt.step(args.warmup)
+        bt.sync()
+        c0 = sum(bt[k].counters()["particle_steps"] for k in range(len(bt)))
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        bt.step(args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        bt.sync()
+        c1 = sum(bt[k].counters()["particle_steps"] for k in range(len(bt)))
+        ps = c1 - c0
+        value = ps / (ms * 1e-3)
+        # duration of the batched launch alone (HIP events around each launch)
+        alive = [sum(bt[k].counters()["n_alive"]) for k in range(len(bt))]
+        units = float(sum(alive))
+        bt.timing(True)
+        bt.step(min(args.steps, 50))
+        kern_ms, n_launch = bt.timing(False)
+        achieved = BYTES_PER_PARTICLE_STEP * units / (kern_ms * 1e-3) / 1e9
+        bpps = stored_traffic("sweep", "pass_batch_kernel")
+        # the same discharges, each advanced alone (one launch per discharge per step)
+        bt.sync()
+        solo_steps = min(args.steps, 20)
+        s0 = sum(bt[k].counters()["particle_steps"] for k in range(len(bt)))
+        torch.cuda.synchronize()
+        ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev2.record(stream)
+        for k in range(len(bt)):
+            B.pic_step(bt[k].h, solo_steps)
+        ev3.record(stream)
+        torch.cuda.synchronize()
+        solo_ms = ev2.elapsed_time(ev3)
+        s1 = sum(bt[k].counters()["particle_steps"] for k in range(len(bt)))
+        solo_value = (s1 - s0) / (solo_ms * 1e-3)
+    finally:
+        bt.close()
+    out = {
+        "metric": "particle-steps/s (push+deposit+MCC)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"argon_sweep_{len(discs)}",
+            "discharges": len(discs),
+            "particles_per_species_initial_total": int(sum(d.n_super[0] for d in discs)),
+            "cells_min": int(min(d.n_cells for d in discs)),
+            "cells_max": int(max(d.n_cells for d in discs)),
+            "alive_particles_mean": ps / args.steps,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None if bpps is None else bpps * units,
+            "traffic_unit": "B per launch",
+            "traffic_GBs": None if bpps is None else bpps * units / (kern_ms * 1e-3) / 1e9,
+            "kernel": "pass_batch_kernel (fused complete+advance, all discharges)",
+            "kernel_ms_mean": kern_ms,
+            "launches_timed": n_launch,
+            "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP,
+        },
+        "solo_sequential": {"value": solo_value, "unit": "particle-steps/s", "steps": solo_steps,
+                            "note": "each discharge advanced alone, one launch per discharge per step"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +192,9 @@ def main():
     import torch
     from paper_1608_04601_amd import binding as B
 
+    if args.workload == "sweep":
+        run_sweep(args, B, torch)
+        return
     disc = workloads_by_name()[args.workload]()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()

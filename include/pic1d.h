@@ -248,12 +248,16 @@ int pic_batch_step(pic_batch* b, int64_t n_steps);
 int pic_batch_sync(pic_batch* b);
 
 /* Borrow the handle of discharge k (0 <= k < n) for the per-discharge calls (moments,
- * counters, particles, fields); valid until pic_batch_free, which frees it.  Do not call
- * pic_free or pic_step on it. */
+ * counters, particles, fields, and pic_step to advance that discharge alone); valid until
+ * pic_batch_free, which frees it.  Do not call pic_free on it. */
 int pic_batch_handle(pic_batch* b, int k, pic_handle** h);
 
 /* Number of workgroups of discharge k in batched launches (for measurement). */
 int pic_batch_blocks(const pic_batch* b, int k, int* blocks);
+
+/* Mean duration (ms) of the batched particle-pass launch over the window started by
+ * pic_batch_timing(b, 1) and read by pic_batch_timing(b, 0) (HIP events on the stream). */
+int pic_batch_timing(pic_batch* b, int start, double* mean_ms, int64_t* n_launches);
 
 void pic_batch_free(pic_batch* b);
 
