@@ -74,24 +74,32 @@ def cpu_baseline(disc, steps):
 
 def run_sweep(args, B, torch):
     """The batched parameter sweep: every discharge of the sweep advanced by one launch per
-    step.  Also times the same discharges advanced one after the other (one launch each per
-    step) for comparison."""
+    step, whole RF periods replayed from one captured HIP graph each (the timed steps are
+    rounded to whole periods).  Also times the batched launch alone, and the same discharges
+    advanced one after the other (one launch each per step) for comparison."""
     discs = workloads_by_name()["sweep"]()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     bt = B.Batch(discs, stream=stream.cuda_stream)
+    spp = int(round(1.0 / (discs[0].rf_frequency_Hz * discs[0].dt_s)))
+    periods = max(1, int(round(args.steps / spp)))
+    steps = periods * spp
     try:
         bt.step(args.warmup)
+        bt.set_graph(spp)
+        bt.step(spp)   # captures the period's graph and replays it once
         bt.sync()
         c0 = sum(bt[k].counters()["particle_steps"] for k in range(len(bt)))
+        r0 = bt.graph_launches()
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
-        bt.step(args.steps)
+        bt.step(steps)
         ev1.record(stream)
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)
         bt.sync()
+        replays = bt.graph_launches() - r0
         c1 = sum(bt[k].counters()["particle_steps"] for k in range(len(bt)))
         ps = c1 - c0
         value = ps / (ms * 1e-3)
@@ -124,9 +132,9 @@ def run_sweep(args, B, torch):
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "steps": steps,
+        "warmup": args.warmup + spp,
+        "ms_per_step": ms / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -138,8 +146,11 @@ def run_sweep(args, B, torch):
             "particles_per_species_initial_total": int(sum(d.n_super[0] for d in discs)),
             "cells_min": int(min(d.n_cells for d in discs)),
             "cells_max": int(max(d.n_cells for d in discs)),
-            "alive_particles_mean": ps / args.steps,
+            "alive_particles_mean": ps / steps,
+            "steps_per_rf_period": spp,
         },
+        "rf_cycles_per_s": periods / (ms * 1e-3),
+        "graph": {"steps_per_graph": spp, "replays_timed": replays},
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,

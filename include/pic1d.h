@@ -240,8 +240,23 @@ typedef struct pic_batch pic_batch;
 int pic_batch_init(const pic_config* cfgs, int n, void* hip_stream, pic_batch** out);
 
 /* Enqueue n steps of every discharge; returns without waiting.  Discharges left with
- * different pending states by per-discharge calls are first brought to the same state. */
+ * different pending states by per-discharge calls are first brought to the same state.
+ * When every discharge is due for reordering in the same step, the reordering runs as one
+ * launch per stage for all of them.  With a graph size set (pic_batch_set_graph), runs of
+ * that many steps are replayed from a captured HIP graph (captured on first use and again
+ * whenever the discharges' reordering phases differ from the captured ones); the rest, and
+ * every step while timing is on, are launched one by one.  Results do not depend on which. */
 int pic_batch_step(pic_batch* b, int64_t n_steps);
+
+/* Steps per captured graph for pic_batch_step: 0 (the default) launches every step
+ * directly; an RF period of the discharges (1 / (f dt) steps) replays one graph per
+ * period.  Must be in [0, 100000]; waits for the stream and drops any captured graph.  The
+ * graph is captured on a private stream of default priority and launched on the batch's
+ * stream; it holds kernel launches only. */
+int pic_batch_set_graph(pic_batch* b, int64_t steps_per_graph);
+
+/* Number of graph replays since the last pic_batch_set_graph (for tests). */
+int pic_batch_graph_launches(const pic_batch* b, int64_t* n);
 
 /* Complete every discharge's pending step with one launch, synchronise, and report the
  * first device error of any discharge. */

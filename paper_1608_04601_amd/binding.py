@@ -20,7 +20,8 @@ EXPORTED = ("pic_init", "pic_step", "pic_sync", "pic_moments", "pic_free", "pic_
             "pic_get_counters", "pic_get_derived", "pic_get_particles", "pic_set_particles",
             "pic_get_fields", "pic_set_record_decisions", "pic_get_decisions", "pic_timing",
             "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
-            "pic_batch_free", "pic_batch_last_error", "pic_batch_timing")
+            "pic_batch_free", "pic_batch_last_error", "pic_batch_timing", "pic_batch_set_graph",
+            "pic_batch_graph_launches")
 
 
 class PicError(RuntimeError):
@@ -116,6 +117,8 @@ def load_library(path: str = None):
         "pic_batch_free": (None, [C.c_void_p]),
         "pic_batch_last_error": (C.c_char_p, [C.c_void_p]),
         "pic_batch_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "pic_batch_set_graph": (C.c_int, [C.c_void_p, C.c_int64]),
+        "pic_batch_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -315,6 +318,15 @@ class Batch:
         ms, n = C.c_double(), C.c_int64()
         _check_batch(self.b, load_library().pic_batch_timing(self.b, 1 if start else 0, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def set_graph(self, steps_per_graph):
+        """Replay runs of steps_per_graph steps from a captured HIP graph (0: launch each step)."""
+        _check_batch(self.b, load_library().pic_batch_set_graph(self.b, int(steps_per_graph)))
+
+    def graph_launches(self):
+        n = C.c_int64()
+        _check_batch(self.b, load_library().pic_batch_graph_launches(self.b, C.byref(n)))
+        return n.value
 
     def blocks(self, k):
         g = C.c_int()

@@ -25,6 +25,8 @@ hipError_t launch_pass_batch(int mode, const Params* batch, const int* seg, int 
                              size_t lds, hipStream_t st);
 hipError_t set_pass_batch_lds_limit(size_t bytes);
 hipError_t pass_batch_occupancy(int threads, size_t lds, int* blocks_per_cu);
+hipError_t launch_sort_batch(const Params* batch, const int* sseg, int nd, int blocks, int max_cells,
+                             hipStream_t st);
 }  // namespace pic
 
 namespace {
@@ -424,6 +426,8 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
             !dev_alloc(h, &h->sort_cnt, (size_t)2 * nc + pic::kMaxSortBlocks) ||
             !dev_alloc(h, &h->sort_cursor, (size_t)2 * nc + pic::kMaxSortBlocks))
             goto fail_init;
+        P.sort_cnt = h->sort_cnt;
+        P.sort_cursor = h->sort_cursor;
         P.tab = tab;
         P.nullbound = nullbound;
         std::vector<float> htab;
@@ -847,6 +851,19 @@ struct pic_batch {
     bool timing = false;
     std::vector<hipEvent_t> ev;
     int64_t n_timed = 0;
+    // reordering of all discharges in one launch per stage: block offsets (n + 1 entries)
+    std::vector<int> sseg;
+    int* dsseg = nullptr;
+    int max_cells = 1;
+    // captured graph of graph_steps steps; valid from the per-discharge reorder phases gsig
+    // (steps since the last reordering) and pending state gpend; it advances the phases to
+    // gend and leaves every discharge's last step pending
+    int64_t graph_steps = 0;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int> gsig, gend;
+    bool gpend = false;
+    hipStream_t cap = nullptr;   // private stream the graph is captured on
+    int64_t graph_launches = 0;
 };
 
 namespace {
@@ -922,10 +939,13 @@ int batch_launch(pic_batch* b, int mode) {
 void pic_batch_free(pic_batch* b) {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     for (pic_handle* h : b->hs) pic_free(h);
     if (b->dparams) (void)hipFree(b->dparams);
     if (b->dseg) (void)hipFree(b->dseg);
+    if (b->dsseg) (void)hipFree(b->dsseg);
     delete b;
 }
 
@@ -979,12 +999,20 @@ int pic_batch_init(const pic_config* cfgs, int n, void* hip_stream, pic_batch** 
         const int g = std::min(cap, std::max(2, (int)std::lround(resident * nk / std::max(total, 1.0))));
         b->seg.push_back(b->seg.back() + g);
     }
+    // reordering blocks: each discharge keeps its own count
+    b->sseg.assign(1, 0);
+    for (int k = 0; k < n; ++k) {
+        b->sseg.push_back(b->sseg.back() + b->hs[k]->sort_blocks);
+        b->max_cells = std::max(b->max_cells, cfgs[k].n_cells);
+    }
     std::vector<pic::Params> hp(n);
     for (int k = 0; k < n; ++k) hp[k] = b->hs[k]->P;
     if ((e = hipMalloc(&b->dparams, sizeof(pic::Params) * n)) != hipSuccess ||
         (e = hipMalloc(&b->dseg, sizeof(int) * (n + 1))) != hipSuccess ||
+        (e = hipMalloc(&b->dsseg, sizeof(int) * (n + 1))) != hipSuccess ||
         (e = hipMemcpy(b->dparams, hp.data(), sizeof(pic::Params) * n, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(b->dseg, b->seg.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess) {
+        (e = hipMemcpy(b->dseg, b->seg.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b->dsseg, b->sseg.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess) {
         const std::string msg = std::string("batch set-up: ") + hipGetErrorString(e);
         pic_batch_free(b);
         return bfail(nullptr, e == hipErrorOutOfMemory ? PIC_ENOMEM : PIC_EHIP, msg);
@@ -993,25 +1021,135 @@ int pic_batch_init(const pic_config* cfgs, int n, void* hip_stream, pic_batch** 
     return PIC_OK;
 }
 
+namespace {
+// One batched step: the particle pass of every discharge, then the reorderings that are
+// due (in one launch per stage when every discharge is due, else one by one).
+int batch_one_step(pic_batch* b) {
+    const int mode = pic::kAdvance | (b->hs[0]->pending ? pic::kComplete : 0);
+    if (batch_launch(b, mode)) return b->status;
+    size_t due = 0;
+    for (pic_handle* h : b->hs) {
+        h->pending = true;
+        if (h->cfg.sort_every > 0 && h->since_sort + 1 >= h->cfg.sort_every) ++due;
+    }
+    if (due == b->hs.size()) {
+        const hipError_t e = pic::launch_sort_batch(b->dparams, b->dsseg, (int)b->hs.size(), b->sseg.back(),
+                                                    b->max_cells, b->stream);
+        if (e != hipSuccess) return bfail(b, PIC_EHIP, std::string("batched sort launch: ") + hipGetErrorString(e));
+        for (pic_handle* h : b->hs) h->since_sort = 0;
+        return PIC_OK;
+    }
+    for (pic_handle* h : b->hs) {
+        if (h->cfg.sort_every > 0 && ++h->since_sort >= h->cfg.sort_every) {
+            if (!hip_ok(h, pic::launch_sort(h->P, h->sort_cnt, h->sort_cursor, h->sort_blocks, h->sort_threads,
+                                            h->stream),
+                        "sort launch"))
+                return batch_status(b);
+            h->since_sort = 0;
+        }
+    }
+    return PIC_OK;
+}
+
+std::vector<int> batch_phases(const pic_batch* b) {
+    std::vector<int> v;
+    for (const pic_handle* h : b->hs) v.push_back(h->since_sort);
+    return v;
+}
+
+// Records graph_steps batched steps, starting from the current reorder phases and pending
+// state (the same for every discharge), into a graph on a private stream.  Nothing runs;
+// the host-side phases and pending flags are put back.
+int batch_capture(pic_batch* b) {
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+        return bfail(b, PIC_EHIP, "hipStreamCreateWithFlags");
+    const std::vector<int> sig = batch_phases(b);
+    const bool pend = b->hs[0]->pending;
+    const hipStream_t user = b->stream;
+    const bool timing = b->timing;
+    b->timing = false;
+    b->stream = b->cap;
+    for (pic_handle* h : b->hs) h->stream = b->cap;
+    hipGraph_t g = nullptr;
+    int rc = PIC_OK;
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        rc = bfail(b, PIC_EHIP, "hipStreamBeginCapture");
+    } else {
+        for (int64_t k = 0; k < b->graph_steps && rc == PIC_OK; ++k) rc = batch_one_step(b);
+        const hipError_t e = hipStreamEndCapture(b->cap, &g);
+        if (rc == PIC_OK && e != hipSuccess) rc = bfail(b, PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    b->gend = batch_phases(b);
+    for (size_t k = 0; k < b->hs.size(); ++k) {
+        b->hs[k]->since_sort = sig[k];
+        b->hs[k]->pending = pend;
+        b->hs[k]->stream = user;
+    }
+    b->stream = user;
+    b->timing = timing;
+    if (rc == PIC_OK) {
+        const hipError_t e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            b->gexec = nullptr;
+            rc = bfail(b, PIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (rc == PIC_OK) {
+        b->gsig = sig;
+        b->gpend = pend;
+    }
+    return rc;
+}
+}  // namespace
+
 int pic_batch_step(pic_batch* b, int64_t n_steps) {
     if (!b) return PIC_EINVAL;
     if (batch_status(b)) return b->status;
     if (n_steps < 0) return bfail(b, PIC_EINVAL, "n_steps must be >= 0");
     if (n_steps > 0 && batch_align(b)) return b->status;
-    for (int64_t k = 0; k < n_steps; ++k) {
-        const int mode = pic::kAdvance | (b->hs[0]->pending ? pic::kComplete : 0);
-        if (batch_launch(b, mode)) return b->status;
-        for (pic_handle* h : b->hs) {
-            h->pending = true;
-            if (h->cfg.sort_every > 0 && ++h->since_sort >= h->cfg.sort_every) {
-                if (!hip_ok(h, pic::launch_sort(h->P, h->sort_cnt, h->sort_cursor, h->sort_blocks, h->sort_threads,
-                                                h->stream),
-                            "sort launch"))
-                    return batch_status(b);
-                h->since_sort = 0;
+    int64_t k = 0;
+    while (k < n_steps) {
+        if (b->graph_steps > 0 && n_steps - k >= b->graph_steps && !b->timing) {
+            if ((!b->gexec || b->hs[0]->pending != b->gpend || batch_phases(b) != b->gsig) && batch_capture(b))
+                return b->status;
+            if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return bfail(b, PIC_EHIP, "hipGraphLaunch");
+            for (size_t q = 0; q < b->hs.size(); ++q) {
+                b->hs[q]->since_sort = b->gend[q];
+                b->hs[q]->pending = true;
             }
+            ++b->graph_launches;
+            k += b->graph_steps;
+            continue;
         }
+        if (batch_one_step(b)) return b->status;
+        ++k;
     }
+    return PIC_OK;
+}
+
+int pic_batch_set_graph(pic_batch* b, int64_t steps_per_graph) {
+    if (!b) return PIC_EINVAL;
+    if (batch_status(b)) return b->status;
+    if (steps_per_graph < 0 || steps_per_graph > 100000)
+        return bfail(b, PIC_EINVAL, "steps_per_graph must be in [0, 100000]");
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, PIC_EHIP, "hipStreamSynchronize");
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    b->graph_steps = steps_per_graph;
+    b->graph_launches = 0;
+    return PIC_OK;
+}
+
+int pic_batch_graph_launches(const pic_batch* b, int64_t* n) {
+    if (!b || !n) return PIC_EINVAL;
+    *n = b->graph_launches;
     return PIC_OK;
 }
 

@@ -1248,15 +1248,16 @@ __device__ __forceinline__ void sort_split(int G, int b, int64_t ns0, int64_t ns
     }
 }
 
-__global__ void __launch_bounds__(1024) sort_count_kernel(Params P, unsigned* cnt) {
-    extern __shared__ __align__(16) unsigned char smem[];
+// Block blk of the G blocks that reorder one discharge.
+__device__ __forceinline__ void sort_count_body(const Params& P, unsigned* cnt, int G, int blk,
+                                                unsigned char* smem) {
     unsigned* h = reinterpret_cast<unsigned*>(smem);   // nc cell counts, then one alive count
     const int nc = P.n_cells, tid = threadIdx.x, nt = blockDim.x;
     const Ctrl* C = P.ctrl;
     const unsigned cur = C->cur;
     int s, Ge;
     int64_t begin, end;
-    sort_split(gridDim.x, blockIdx.x, C->n_slots[0], C->n_slots[1], s, Ge, begin, end);
+    sort_split(G, blk, C->n_slots[0], C->n_slots[1], s, Ge, begin, end);
     for (int i = tid; i <= nc; i += nt) h[i] = 0;
     __syncthreads();
     const float* X = bufsel(P.x, cur, s);
@@ -1265,7 +1266,7 @@ __global__ void __launch_bounds__(1024) sort_count_kernel(Params P, unsigned* cn
         for (int64_t v = begin + tid; v < end; v += nt) c += X[v] > 0.0f ? 1u : 0u;
         if (c) atomicAdd(&h[nc], c);
         __syncthreads();
-        if (tid == 0) cnt[2 * nc + blockIdx.x] = h[nc];
+        if (tid == 0) cnt[2 * nc + blk] = h[nc];
     } else {
         for (int64_t v = begin + tid; v < end; v += nt) {
             const float x = X[v];
@@ -1280,6 +1281,11 @@ __global__ void __launch_bounds__(1024) sort_count_kernel(Params P, unsigned* cn
         for (int i = tid; i < nc; i += nt)
             if (h[i]) atomicAdd(&cnt[s * nc + i], h[i]);
     }
+}
+
+__global__ void __launch_bounds__(1024) sort_count_kernel(Params P, unsigned* cnt) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    sort_count_body(P, cnt, gridDim.x, blockIdx.x, smem);
 }
 
 // Exclusive scan of a[0..n) into o (one block of 1024 threads); a is cleared.  Returns the
@@ -1309,8 +1315,7 @@ __device__ unsigned block_excl_scan(unsigned* a, unsigned* o, int n, unsigned* s
     return total;
 }
 
-__global__ void __launch_bounds__(1024) sort_scan_kernel(Params P, unsigned* cnt, unsigned* cursor, int G) {
-    __shared__ unsigned sh[1024];
+__device__ __forceinline__ void sort_scan_body(const Params& P, unsigned* cnt, unsigned* cursor, int G, unsigned* sh) {
     const int nc = P.n_cells;
     Ctrl* C = P.ctrl;
     int s, Ge;
@@ -1331,8 +1336,13 @@ __global__ void __launch_bounds__(1024) sort_scan_kernel(Params P, unsigned* cnt
     }
 }
 
-__global__ void __launch_bounds__(1024) sort_scatter_kernel(Params P, unsigned* cursor) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__global__ void __launch_bounds__(1024) sort_scan_kernel(Params P, unsigned* cnt, unsigned* cursor, int G) {
+    __shared__ unsigned sh[1024];
+    sort_scan_body(P, cnt, cursor, G, sh);
+}
+
+__device__ __forceinline__ void sort_scatter_body(const Params& P, unsigned* cursor, int G, int blk,
+                                                  unsigned char* smem) {
     const int nc = P.n_cells, tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
     unsigned* h = reinterpret_cast<unsigned*>(smem);   // nc local counts, then cursors
@@ -1343,7 +1353,7 @@ __global__ void __launch_bounds__(1024) sort_scatter_kernel(Params P, unsigned* 
     const unsigned cur = C->cur, nxt = cur ^ 1u;
     int s, Ge;
     int64_t begin, end;
-    sort_split(gridDim.x, blockIdx.x, C->n_slots[0], C->n_slots[1], s, Ge, begin, end);
+    sort_split(G, blk, C->n_slots[0], C->n_slots[1], s, Ge, begin, end);
     const float* X = bufsel(P.x, cur, s);
     const float* VX = bufsel(P.vx, cur, s);
     const float* VY = bufsel(P.vy, cur, s);
@@ -1357,7 +1367,7 @@ __global__ void __launch_bounds__(1024) sort_scatter_kernel(Params P, unsigned* 
     if (!P.sort_cells[s]) {
         // order-keeping compaction: this range's alive particles go, in order, to
         // [cursor[2 nc + b], ...)
-        unsigned pos = cursor[2 * nc + blockIdx.x];
+        unsigned pos = cursor[2 * nc + blk];
         for (int64_t vb = begin; vb < end; vb += nt) {
             const int64_t v = vb + tid;
             const float x = v < end ? X[v] : -1.0f;
@@ -1421,7 +1431,7 @@ __global__ void __launch_bounds__(1024) sort_scatter_kernel(Params P, unsigned* 
     __syncthreads();
     if (tid == 0) {
         const unsigned prev = atomicAdd(&C->done, 1u);
-        flag[0] = (prev == gridDim.x - 1) ? 1u : 0u;
+        flag[0] = (prev == (unsigned)G - 1u) ? 1u : 0u;
     }
     __syncthreads();
     if (!flag[0] || tid != 0) return;
@@ -1429,6 +1439,47 @@ __global__ void __launch_bounds__(1024) sort_scatter_kernel(Params P, unsigned* 
     C->n_slots[1] = (int64_t)ld_agent(&C->sort_alive[1]);
     C->cur = nxt;
     C->done = 0;
+}
+
+__global__ void __launch_bounds__(1024) sort_scatter_kernel(Params P, unsigned* cursor) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    sort_scatter_body(P, cursor, gridDim.x, blockIdx.x, smem);
+}
+
+// The same three stages for several discharges at once: discharge k owns blocks
+// [sseg[k], sseg[k + 1]) of the count and scatter launches and block k of the scan launch,
+// and keeps its histograms in its own P.sort_cnt / P.sort_cursor.
+__device__ __forceinline__ int batch_member(const int* seg, int nd, int b) {
+    int lo = 0, hi = nd;   // seg[lo] <= b < seg[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(1024) sort_count_batch_kernel(const Params* __restrict__ batch,
+                                                                const int* __restrict__ sseg, int nd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int k = batch_member(sseg, nd, blockIdx.x);
+    const Params& P = batch[k];
+    sort_count_body(P, P.sort_cnt, sseg[k + 1] - sseg[k], blockIdx.x - sseg[k], smem);
+}
+
+__global__ void __launch_bounds__(1024) sort_scan_batch_kernel(const Params* __restrict__ batch,
+                                                               const int* __restrict__ sseg) {
+    __shared__ unsigned sh[1024];
+    const int k = blockIdx.x;
+    const Params& P = batch[k];
+    sort_scan_body(P, P.sort_cnt, P.sort_cursor, sseg[k + 1] - sseg[k], sh);
+}
+
+__global__ void __launch_bounds__(1024) sort_scatter_batch_kernel(const Params* __restrict__ batch,
+                                                                  const int* __restrict__ sseg, int nd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int k = batch_member(sseg, nd, blockIdx.x);
+    const Params& P = batch[k];
+    sort_scatter_body(P, P.sort_cursor, sseg[k + 1] - sseg[k], blockIdx.x - sseg[k], smem);
 }
 
 // Moment window reset (kernel rather than a memset so it can sit in a captured graph).
@@ -1533,6 +1584,21 @@ hipError_t launch_sort(const Params& P, unsigned* cnt, unsigned* cursor, int blo
     if (e != hipSuccess) return e;
     const size_t lds_scatter = (size_t)2 * P.n_cells * sizeof(unsigned) + 17 * sizeof(unsigned);
     hipLaunchKernelGGL(sort_scatter_kernel, dim3(blocks), dim3(threads), lds_scatter, st, P, cursor);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_batch(const Params* batch, const int* sseg, int nd, int blocks, int max_cells,
+                             hipStream_t st) {
+    if (nd < 1 || blocks < 2 * nd || max_cells < 1) return hipErrorInvalidValue;
+    const size_t lds_count = (size_t)(max_cells + 1) * sizeof(unsigned);
+    hipLaunchKernelGGL(sort_count_batch_kernel, dim3(blocks), dim3(1024), lds_count, st, batch, sseg, nd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sort_scan_batch_kernel, dim3(nd), dim3(1024), 0, st, batch, sseg);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds_scatter = (size_t)2 * max_cells * sizeof(unsigned) + 17 * sizeof(unsigned);
+    hipLaunchKernelGGL(sort_scatter_batch_kernel, dim3(blocks), dim3(1024), lds_scatter, st, batch, sseg, nd);
     return hipGetLastError();
 }
 

@@ -114,6 +114,8 @@ struct Params {
     double mscale[2];    // fixed-point scale of the second moment quantity per species
     uint32_t* birth_parent;   // [max_births]
     unsigned long long* birth_order;   // ranking scratch: (parent id << 32 | birth index) [max_births]
+    unsigned* sort_cnt;       // reordering histograms [2 n_cells + kMaxSortBlocks]
+    unsigned* sort_cursor;    // their exclusive prefix sums [2 n_cells + kMaxSortBlocks]
     int8_t* dec[2];      // decision record per slot, or null
     const float* tab;    // n_gas * sigma tables [1/m]
     const float* nullbound;   // [kNullBins + 1] electron collision-frequency bounds [1/s]

@@ -175,7 +175,8 @@ def large_argon(seed: int = 0, n_super: int = 25_000_000) -> Discharge:
 def sweep_argon(n_discharges: int = 64, seed: int = 0) -> Tuple[Discharge, ...]:
     """Pressure/voltage sweep of argon-like discharges drawn from default_rng(seed):
     p ~ U(10, 80) Pa, V0 ~ U(100, 400) V, d ~ U(2, 3) cm, cells ~ U{256..1024} rounded to
-    a multiple of 64, particles per species log-uniform in [1e5, 2e6], dt = T_rf/2000."""
+    a multiple of 64, particles per species log-uniform in [1e5, 2e6], dt = T_rf/2000.  The
+    uniform start ionises strongly in its first periods: storage is 8x the initial count."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n_discharges):
@@ -190,6 +191,6 @@ def sweep_argon(n_discharges: int = 64, seed: int = 0) -> Tuple[Discharge, ...]:
             name=f"sweep{k:02d}", gap_m=d, pressure_Pa=p, gas_temperature_K=300.0,
             gas_mass_amu=AMU_AR, rf_voltage_V=v0, rf_frequency_Hz=F_RF, dt_s=1.0 / (F_RF * 2000),
             n_cells=nc, n_init_m3=1e15, te_init_eV=2.0, ti_init_eV=0.026,
-            n_super=(npart, npart), capacity=(2 * npart, 2 * npart), seed=seed * 1000 + k,
-            processes=argon_like(top, top), sort_every=20, moments_every=1))
+            n_super=(npart, npart), capacity=(8 * npart, 8 * npart), seed=seed * 1000 + k,
+            processes=argon_like(top, top), sort_every=20, moments_every=1, max_births_per_step=1 << 18))
     return tuple(out)
