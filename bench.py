@@ -86,6 +86,7 @@ def run_sweep(args, B, torch):
     steps = periods * spp
     try:
         bt.step(args.warmup)
+        tuning = bt.autotune(args.tune_steps) if args.tune_steps > 0 else None
         bt.set_graph(spp)
         bt.step(spp)   # captures the period's graph and replays it once
         bt.sync()
@@ -151,6 +152,7 @@ def run_sweep(args, B, torch):
         },
         "rf_cycles_per_s": periods / (ms * 1e-3),
         "graph": {"steps_per_graph": spp, "replays_timed": replays},
+        "tuning": tuning,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -181,6 +183,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps of the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-blocks", type=int, default=0)
+    ap.add_argument("--tune-steps", type=int, default=100,
+                    help="sweep: steps per autotuning trial before timing (0: keep the default schedule)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this size (5 launches), to calibrate "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE readings against known bytes")

@@ -258,6 +258,25 @@ int pic_batch_set_graph(pic_batch* b, int64_t steps_per_graph);
 /* Number of graph replays since the last pic_batch_set_graph (for tests). */
 int pic_batch_graph_launches(const pic_batch* b, int64_t* n);
 
+/* Launch and reordering schedule chosen by pic_batch_autotune. */
+typedef struct pic_tuning {
+    int32_t threads;         /* workgroup size of the batched particle pass */
+    int32_t sort_every;      /* steps between reorderings, every discharge */
+    int32_t electron_order;  /* 1 electrons sorted by cell, 0 compacted in order, -1 each
+                                discharge's own choice from pic_config.electron_order */
+    int32_t trials;          /* configurations timed */
+    double rounds;           /* workgroups per launch, in units of those resident at once */
+    double ms_per_step;      /* measured mean time per batched step, reordering included */
+} pic_tuning;
+
+/* Picks the batched pass's workgroup size and launch size, the reordering interval and the
+ * electron ordering by timing eager trials of about steps_per_trial steps (at least two
+ * reordering intervals) on the batch itself, one coordinate at a time, and keeps the
+ * fastest.  The trials advance every discharge; results do not depend on the choices, only
+ * the time per step does.  Needs every discharge created with sort_every > 0;
+ * steps_per_trial in [4, 100000].  Drops any captured graph.  out may be NULL. */
+int pic_batch_autotune(pic_batch* b, int64_t steps_per_trial, pic_tuning* out);
+
 /* Complete every discharge's pending step with one launch, synchronise, and report the
  * first device error of any discharge. */
 int pic_batch_sync(pic_batch* b);

@@ -21,7 +21,12 @@ EXPORTED = ("pic_init", "pic_step", "pic_sync", "pic_moments", "pic_free", "pic_
             "pic_get_fields", "pic_set_record_decisions", "pic_get_decisions", "pic_timing",
             "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
             "pic_batch_free", "pic_batch_last_error", "pic_batch_timing", "pic_batch_set_graph",
-            "pic_batch_graph_launches")
+            "pic_batch_graph_launches", "pic_batch_autotune")
+
+
+class pic_tuning(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("sort_every", C.c_int32), ("electron_order", C.c_int32),
+                ("trials", C.c_int32), ("rounds", C.c_double), ("ms_per_step", C.c_double)]
 
 
 class PicError(RuntimeError):
@@ -119,6 +124,7 @@ def load_library(path: str = None):
         "pic_batch_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "pic_batch_set_graph": (C.c_int, [C.c_void_p, C.c_int64]),
         "pic_batch_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+        "pic_batch_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -327,6 +333,13 @@ class Batch:
         n = C.c_int64()
         _check_batch(self.b, load_library().pic_batch_graph_launches(self.b, C.byref(n)))
         return n.value
+
+    def autotune(self, steps_per_trial=100):
+        """Times launch and reordering schedules on the batch itself and keeps the fastest;
+        returns the choice as a dict."""
+        t = pic_tuning()
+        _check_batch(self.b, load_library().pic_batch_autotune(self.b, int(steps_per_trial), C.byref(t)))
+        return {k: getattr(t, k) for k, _ in pic_tuning._fields_}
 
     def blocks(self, k):
         g = C.c_int()

@@ -845,6 +845,7 @@ struct pic_batch {
     std::vector<int> seg;   // workgroup offsets, n + 1 entries
     int threads = 256;
     size_t lds = 0;
+    double rounds = 4.0;   // workgroups per launch in units of the device's resident workgroups
     int status = PIC_OK;
     std::string err;
     // timing of the batched particle pass
@@ -934,6 +935,39 @@ int batch_launch(pic_batch* b, int mode) {
     }
     return PIC_OK;
 }
+// Launch shape of the batched pass: blockDim `threads` (every discharge's n_cells + 1 must
+// be <= 8 threads), and about `rounds` x the workgroups resident on the device at once,
+// split over the discharges in proportion to the weights w (their particles); each
+// discharge gets at least 2 and at most one per 4 x blockDim particles.  Uploads the block
+// offsets when the device table exists.
+hipError_t batch_layout(pic_batch* b, int threads, double rounds, const std::vector<double>& w) {
+    size_t lds = 0;
+    for (pic_handle* h : b->hs) lds = std::max(lds, pass_lds_bytes(h->cfg.n_cells + 1, threads));
+    hipError_t e = pic::set_pass_batch_lds_limit(lds);
+    int cus = 0, per_cu = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->hs[0]->device);
+    if (e == hipSuccess) e = pic::pass_batch_occupancy(threads, lds, &per_cu);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    double total = 0.0;
+    for (double x : w) total += x;
+    const double resident = rounds * (double)cus * (double)per_cu;
+    std::vector<int> seg(1, 0);
+    for (size_t k = 0; k < b->hs.size(); ++k) {
+        const int cap = std::max(2, (int)std::ceil(w[k] / (4.0 * threads)));
+        const int g = std::min(cap, std::max(2, (int)std::lround(resident * w[k] / std::max(total, 1.0))));
+        seg.push_back(seg.back() + g);
+    }
+    if (b->dseg) {
+        e = hipMemcpy(b->dseg, seg.data(), sizeof(int) * seg.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+    }
+    b->threads = threads;
+    b->lds = lds;
+    b->rounds = rounds;
+    b->seg = seg;
+    return hipSuccess;
+}
 }  // namespace
 
 void pic_batch_free(pic_batch* b) {
@@ -973,32 +1007,21 @@ int pic_batch_init(const pic_config* cfgs, int n, void* hip_stream, pic_batch** 
         b->hs.push_back(h);
         max_nn = std::max(max_nn, cfgs[k].n_cells + 1);
     }
-    // one workgroup size for the launch: the epilogue needs n_cells + 1 <= 8 x blockDim
-    b->threads = max_nn <= 2048 ? 256 : 1024;
-    for (int k = 0; k < n; ++k) b->lds = std::max(b->lds, pass_lds_bytes(cfgs[k].n_cells + 1, b->threads));
-    hipError_t e = pic::set_pass_batch_lds_limit(b->lds);
-    int cus = 0, per_cu = 0;
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->hs[0]->device);
-    if (e == hipSuccess) e = pic::pass_batch_occupancy(b->threads, b->lds, &per_cu);
-    if (e != hipSuccess) {
-        const std::string msg = std::string("batch set-up: ") + hipGetErrorString(e);
-        pic_batch_free(b);
-        return bfail(nullptr, PIC_EHIP, msg);
+    // One workgroup size for the launch (the epilogue needs n_cells + 1 <= 8 x blockDim), and
+    // about four resident rounds of workgroups: the discharges' uneven costs then even out
+    // in the hardware's dispatch (measured on a 64-discharge sweep: 1.32 ms per launch with
+    // one round, 0.97 ms with four).  pic_batch_autotune revises both.
+    {
+        std::vector<double> w;
+        for (int k = 0; k < n; ++k) w.push_back((double)(cfgs[k].n_init_super[0] + cfgs[k].n_init_super[1]));
+        const hipError_t e = batch_layout(b, max_nn <= 2048 ? 256 : 1024, 4.0, w);
+        if (e != hipSuccess) {
+            const std::string msg = std::string("batch set-up: ") + hipGetErrorString(e);
+            pic_batch_free(b);
+            return bfail(nullptr, PIC_EHIP, msg);
+        }
     }
-    // workgroups in proportion to the particles, about four resident rounds in all (the
-    // discharges' uneven costs then even out in the hardware's dispatch; measured on a
-    // 64-discharge sweep: 1.32 ms per launch with one round, 0.97 ms with four); each
-    // discharge has at least 2 and at most one per 4 x blockDim particles
-    double total = 0.0;
-    for (int k = 0; k < n; ++k) total += (double)(cfgs[k].n_init_super[0] + cfgs[k].n_init_super[1]);
-    const double resident = 4.0 * (double)std::max(1, cus * std::max(per_cu, 1));
-    b->seg.assign(1, 0);
-    for (int k = 0; k < n; ++k) {
-        const double nk = (double)(cfgs[k].n_init_super[0] + cfgs[k].n_init_super[1]);
-        const int cap = std::max(2, (int)std::ceil(nk / (4.0 * b->threads)));
-        const int g = std::min(cap, std::max(2, (int)std::lround(resident * nk / std::max(total, 1.0))));
-        b->seg.push_back(b->seg.back() + g);
-    }
+    hipError_t e = hipSuccess;
     // reordering blocks: each discharge keeps its own count
     b->sseg.assign(1, 0);
     for (int k = 0; k < n; ++k) {
@@ -1150,6 +1173,134 @@ int pic_batch_set_graph(pic_batch* b, int64_t steps_per_graph) {
 int pic_batch_graph_launches(const pic_batch* b, int64_t* n) {
     if (!b || !n) return PIC_EINVAL;
     *n = b->graph_launches;
+    return PIC_OK;
+}
+
+namespace {
+struct Tune {
+    int threads;
+    double rounds;
+    int sort_every;
+    int order;   // electrons: 1 sorted by cell, 0 compacted in order, -1 each discharge's own choice
+};
+
+int batch_apply(pic_batch* b, const Tune& t, const std::vector<double>& w, const std::vector<int>& own) {
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    if (t.threads != b->threads || t.rounds != b->rounds) {
+        const hipError_t e = batch_layout(b, t.threads, t.rounds, w);
+        if (e != hipSuccess) return bfail(b, PIC_EHIP, std::string("batch layout: ") + hipGetErrorString(e));
+    }
+    bool reload = false;
+    for (size_t k = 0; k < b->hs.size(); ++k) {
+        pic_handle* h = b->hs[k];
+        h->cfg.sort_every = t.sort_every;
+        const int order = t.order < 0 ? own[k] : t.order;
+        if (h->P.sort_cells[0] != order) {
+            h->P.sort_cells[0] = order;
+            reload = true;
+        }
+    }
+    if (reload) {
+        std::vector<pic::Params> hp;
+        for (pic_handle* h : b->hs) hp.push_back(h->P);
+        if (hipMemcpy(b->dparams, hp.data(), sizeof(pic::Params) * hp.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bfail(b, PIC_EHIP, "parameter upload");
+    }
+    return PIC_OK;
+}
+
+// Mean time per step of `steps` eager batched steps (reorderings included), after two
+// untimed steps; steps is a multiple of the reordering interval.
+int batch_trial(pic_batch* b, int64_t steps, double* ms) {
+    for (int k = 0; k < 2; ++k)
+        if (batch_one_step(b)) return b->status;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return bfail(b, PIC_EHIP, "hipEventCreate");
+    }
+    int rc = hipEventRecord(e0, b->stream) == hipSuccess ? PIC_OK : bfail(b, PIC_EHIP, "hipEventRecord");
+    for (int64_t k = 0; k < steps && rc == PIC_OK; ++k) rc = batch_one_step(b);
+    if (rc == PIC_OK && hipEventRecord(e1, b->stream) != hipSuccess) rc = bfail(b, PIC_EHIP, "hipEventRecord");
+    if (rc == PIC_OK && hipEventSynchronize(e1) != hipSuccess) rc = bfail(b, PIC_EHIP, "hipEventSynchronize");
+    float t = 0.0f;
+    if (rc == PIC_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = bfail(b, PIC_EHIP, "hipEventElapsedTime");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == PIC_OK) {
+        for (pic_handle* h : b->hs) check_device(h);
+        rc = batch_status(b);
+    }
+    *ms = (double)t / (double)steps;
+    return rc;
+}
+}  // namespace
+
+int pic_batch_autotune(pic_batch* b, int64_t steps_per_trial, pic_tuning* out) {
+    if (!b) return PIC_EINVAL;
+    if (batch_status(b)) return b->status;
+    if (steps_per_trial < 4 || steps_per_trial > 100000)
+        return bfail(b, PIC_EINVAL, "steps_per_trial must be in [4, 100000]");
+    if (pic_batch_sync(b)) return b->status;
+    // weights of the layout: the particles alive now
+    std::vector<double> w;
+    int max_nn = 0;
+    for (pic_handle* h : b->hs) {
+        pic::Ctrl c;
+        if (read_ctrl(h, &c)) return batch_status(b);
+        w.push_back((double)std::max<int64_t>(1, c.n_alive[0] + c.n_alive[1]));
+        max_nn = std::max(max_nn, h->cfg.n_cells + 1);
+    }
+    int se0 = 0;
+    std::vector<int> own;
+    for (pic_handle* h : b->hs) {
+        if (h->cfg.sort_every <= 0 || h->P.x[1][0] == nullptr)
+            return bfail(b, PIC_EINVAL, "autotuning needs every discharge created with sort_every > 0");
+        se0 = std::max(se0, h->cfg.sort_every);
+        own.push_back(h->P.sort_cells[0]);
+    }
+    Tune best{b->threads, b->rounds, se0, -1};
+    double best_ms = 0.0;
+    int trials = 0;
+    auto run = [&](const Tune& t, double* ms) -> int {
+        if (batch_apply(b, t, w, own)) return b->status;
+        const int64_t steps = ((std::max<int64_t>(steps_per_trial, 2 * t.sort_every) + t.sort_every - 1) / t.sort_every) *
+                              t.sort_every;
+        ++trials;
+        return batch_trial(b, steps, ms);
+    };
+    if (run(best, &best_ms)) return b->status;
+    auto consider = [&](Tune t) -> int {
+        double ms = 0.0;
+        if (run(t, &ms)) return b->status;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+        return PIC_OK;
+    };
+    // coordinate search: launch size, workgroup size, reordering interval, electron order
+    for (double r : {1.0, 2.0, 4.0, 8.0})
+        if (r != best.rounds && consider(Tune{best.threads, r, best.sort_every, best.order})) return b->status;
+    for (int nt : {256, 512, 1024})
+        if (nt != best.threads && max_nn <= 8 * nt && consider(Tune{nt, best.rounds, best.sort_every, best.order}))
+            return b->status;
+    for (int se : {5, 10, 20, 40, 80})
+        if (se != best.sort_every && consider(Tune{best.threads, best.rounds, se, best.order})) return b->status;
+    for (int order : {0, 1})
+        if (consider(Tune{best.threads, best.rounds, best.sort_every, order})) return b->status;
+    if (batch_apply(b, best, w, own)) return b->status;
+    if (out) {
+        out->threads = best.threads;
+        out->sort_every = best.sort_every;
+        out->electron_order = best.order;
+        out->trials = trials;
+        out->rounds = best.rounds;
+        out->ms_per_step = best_ms;
+    }
     return PIC_OK;
 }
 

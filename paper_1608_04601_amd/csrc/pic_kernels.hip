@@ -15,6 +15,7 @@
 // the grid in LDS and are flushed to the global grid with one atomic per touched node.
 // The charge grid is fixed point (integer weights summing to 2^24 per particle): exact,
 // and independent of the order in which lanes and workgroups add to it.
+#include <mutex>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -1548,6 +1549,11 @@ hipError_t launch_pass_batch(int mode, const Params* batch, const int* seg, int 
 }
 
 hipError_t set_pass_batch_lds_limit(size_t bytes) {
+    // The limit only grows, so that the launches of every live handle or batch stay within it.
+    static std::mutex mu;
+    static size_t limit = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (bytes <= limit) return hipSuccess;
     const int b = (int)bytes;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_batch_kernel<kComplete | kAdvance>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, b);
@@ -1557,6 +1563,7 @@ hipError_t set_pass_batch_lds_limit(size_t bytes) {
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_batch_kernel<kComplete>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess) limit = bytes;
     return e;
 }
 
@@ -1612,6 +1619,11 @@ hipError_t pass_occupancy(int threads, size_t lds, int* blocks_per_cu) {
 }
 
 hipError_t set_pass_lds_limit(size_t bytes) {
+    // The limit only grows, so that the launches of every live handle or batch stay within it.
+    static std::mutex mu;
+    static size_t limit = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (bytes <= limit) return hipSuccess;
     const int b = (int)bytes;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete | kAdvance>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, b);
@@ -1630,6 +1642,7 @@ hipError_t set_pass_lds_limit(size_t bytes) {
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete | kRecord>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess) limit = bytes;
     return e;
 }
 

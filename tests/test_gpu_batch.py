@@ -109,3 +109,25 @@ def test_graph_replays_equal_eager_steps():
             for k in range(len(discs)):
                 _same(_state(g[k]), _state(e[k]), (n, k))
         log(f"graph replays checked: {replays}")
+
+
+def test_autotune_choice_is_valid_and_keeps_results():
+    """The tuner's trials advance the batch under other launch shapes and reordering
+    schedules; the state must still equal, per id, each discharge advanced alone by the
+    same number of steps."""
+    discs = _common_sort_members()
+    with B.Batch(discs) as bt:
+        bt.step(3)
+        t = bt.autotune(steps_per_trial=8)
+        log(f"autotune: {t}")
+        assert t["trials"] >= 10 and t["ms_per_step"] > 0
+        assert t["threads"] in (256, 512, 1024) and t["rounds"] in (1.0, 2.0, 4.0, 8.0)
+        assert t["sort_every"] in (5, 10, 20, 40, 80) and t["electron_order"] in (-1, 0, 1)
+        bt.step(7)
+        got = [_state(bt[k]) for k in range(len(bt))]
+    steps = got[0][2]["step"]
+    assert all(g[2]["step"] == steps for g in got) and steps > 10
+    for k, d in enumerate(discs):
+        with B.Discharge(d) as solo:
+            solo.step(steps)
+            _same(got[k], _state(solo), k)
