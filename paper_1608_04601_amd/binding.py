@@ -21,7 +21,9 @@ EXPORTED = ("pic_init", "pic_step", "pic_sync", "pic_moments", "pic_free", "pic_
             "pic_get_fields", "pic_set_record_decisions", "pic_get_decisions", "pic_timing",
             "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
             "pic_batch_free", "pic_batch_last_error", "pic_batch_timing", "pic_batch_set_graph",
-            "pic_batch_graph_launches", "pic_batch_autotune")
+            "pic_batch_graph_launches", "pic_batch_autotune",
+            "mlp_init", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_gradient",
+            "mlp_train_step", "mlp_free", "mlp_last_error")
 
 
 class pic_tuning(C.Structure):
@@ -125,6 +127,16 @@ def load_library(path: str = None):
         "pic_batch_set_graph": (C.c_int, [C.c_void_p, C.c_int64]),
         "pic_batch_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
         "pic_batch_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
+        "mlp_init": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
+                               C.POINTER(C.c_void_p)]),
+        "mlp_num_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+        "mlp_set_params": (C.c_int, [C.c_void_p, fp, C.c_int64]),
+        "mlp_get_params": (C.c_int, [C.c_void_p, fp, C.c_int64]),
+        "mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+        "mlp_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, fp, dp]),
+        "mlp_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, fp]),
+        "mlp_free": (None, [C.c_void_p]),
+        "mlp_last_error": (C.c_char_p, [C.c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -429,6 +441,80 @@ class Discharge:
     def close(self):
         if self.h:
             pic_free(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_mlp(h, rc):
+    if rc != PIC_OK:
+        msg = load_library().mlp_last_error(h)
+        raise PicError(rc, msg.decode() if msg else "")
+
+
+class Mlp:
+    """The surrogate network (include/surrogate.h).  x, t and y are device tensors (FP32,
+    row-major, contiguous) on the handle's device; only their pointers cross the ABI."""
+
+    def __init__(self, n_in, width, depth, n_out, max_batch, seed=0, stream=None):
+        L = load_library()
+        h = C.c_void_p()
+        _check_mlp(None, L.mlp_init(int(n_in), int(width), int(depth), int(n_out), int(max_batch), int(seed),
+                                    C.c_void_p(stream) if stream else None, C.byref(h)))
+        self.h, self.n_in, self.n_out, self.max_batch = h, int(n_in), int(n_out), int(max_batch)
+        n = C.c_int64()
+        _check_mlp(self.h, L.mlp_num_params(self.h, C.byref(n)))
+        self.n_params = n.value
+
+    @staticmethod
+    def _ptr(t, cols):
+        assert t.is_cuda and t.dtype.is_floating_point and t.element_size() == 4 and t.is_contiguous()
+        assert t.dim() == 2 and t.shape[1] == cols
+        return C.c_void_p(t.data_ptr())
+
+    def get_params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check_mlp(self.h, load_library().mlp_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float)),
+                                                         self.n_params))
+        return out
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == self.n_params
+        _check_mlp(self.h, load_library().mlp_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+    def forward(self, x, y):
+        _check_mlp(self.h, load_library().mlp_forward(self.h, self._ptr(x, self.n_in), x.shape[0],
+                                                      self._ptr(y, self.n_out)))
+
+    def gradient(self, x, t):
+        g = np.empty(self.n_params, dtype=np.float32)
+        loss = C.c_double()
+        _check_mlp(self.h, load_library().mlp_gradient(self.h, self._ptr(x, self.n_in), self._ptr(t, self.n_out),
+                                                       x.shape[0], g.ctypes.data_as(C.POINTER(C.c_float)),
+                                                       C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, x, t, lr, want_loss=False):
+        loss = C.c_float()
+        _check_mlp(self.h, load_library().mlp_train_step(self.h, self._ptr(x, self.n_in), self._ptr(t, self.n_out),
+                                                         x.shape[0], float(lr),
+                                                         C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if self.h:
+            load_library().mlp_free(self.h)
             self.h = None
 
     def __enter__(self):

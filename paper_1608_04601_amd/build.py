@@ -12,7 +12,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libpic1d.so")
-SOURCES = [os.path.join(CSRC, "pic_kernels.hip"), os.path.join(CSRC, "pic_api.cpp")]
+SOURCES = [os.path.join(CSRC, "pic_kernels.hip"), os.path.join(CSRC, "pic_api.cpp"),
+           os.path.join(CSRC, "mlp_kernels.hip"), os.path.join(CSRC, "mlp_api.cpp")]
 ARCH = "gfx950"
 
 

@@ -1,0 +1,184 @@
+// Kernels of the warm-start surrogate: a multilayer perceptron trained and evaluated in
+// BF16 on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation), with FP32
+// master weights and Adam (Kingma & Ba 2015, Algorithm 1).
+//
+// Every layer product is one GEMM  C[M x N] = A[M x K] B[K x N]  with element strides
+// (so the transposed products of the backward pass need no transposed copies) and a
+// fused epilogue: + bias[n], ReLU, a ReLU-derivative mask, FP32 and/or BF16 output.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mlp_types.hpp"
+
+namespace mlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (NaN stays a quiet NaN).
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x0040u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Workgroup tile 64 x 64, K staged 32 at a time through LDS; four waves in a 2 x 2
+// arrangement, each owning 32 x 32 of C as 2 x 2 MFMA blocks of 16 x 16.  LDS holds the A
+// tile m-major and the B tile n-major, both with K contiguous, so that a lane's eight
+// K-consecutive operands are one 16-byte LDS read: for the 16x16x32 BF16 MFMA, lane l
+// supplies A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16] (i = 0..7) and receives
+// D[4 (l / 16) + q][l % 16] (q = 0..3).
+constexpr int kBM = 64, kBN = 64, kBK = 32, kLDK = kBK + 8;
+
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
+    __shared__ __align__(16) uint16_t As[kBM * kLDK];
+    __shared__ __align__(16) uint16_t Bs[kBN * kLDK];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+        for (int e = tid; e < kBM * kBK; e += 256) {
+            const int r = e / kBK, c = e % kBK;
+            const int64_t m = m0 + r, k = k0 + c;
+            As[r * kLDK + c] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (uint16_t)0;
+        }
+        for (int e = tid; e < kBN * kBK; e += 256) {
+            const int r = e / kBK, c = e % kBK;
+            const int64_t n = n0 + r, k = k0 + c;
+            Bs[r * kLDK + c] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (uint16_t)0;
+        }
+        __syncthreads();
+        bf16x8 a[2], b[2];
+        for (int i = 0; i < 2; ++i) {
+            a[i] = *reinterpret_cast<const bf16x8*>(&As[(wm + 16 * i + (lane & 15)) * kLDK + 8 * (lane >> 4)]);
+            b[i] = *reinterpret_cast<const bf16x8*>(&Bs[(wn + 16 * i + (lane & 15)) * kLDK + 8 * (lane >> 4)]);
+        }
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int q = 0; q < 4; ++q) {
+                const int64_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+                const int64_t n = n0 + wn + 16 * j + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[i][j][q];
+                if (g.bias) v += g.bias[n];
+                if (g.relu) v = fmaxf(v, 0.0f);
+                if (g.mask && !(from_bf16(g.mask[m * g.ldc + n]) > 0.0f)) v = 0.0f;
+                if (g.Cf) g.Cf[m * g.ldc + n] = v;
+                if (g.Cb) g.Cb[m * g.ldc + n] = to_bf16(v);
+            }
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = to_bf16(x[i]);
+}
+
+__global__ void fill_kernel(float* __restrict__ p, int64_t n, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// dL/dy of L = sum (y - t)^2 / n: 2 (y - t) / n, in FP32 and BF16; the loss sum goes to
+// *loss (one atomic per workgroup).
+__global__ void __launch_bounds__(256) loss_grad_kernel(const float* __restrict__ y, const float* __restrict__ t,
+                                                        int64_t n, float* __restrict__ df,
+                                                        uint16_t* __restrict__ db, float* __restrict__ loss) {
+    __shared__ float part[4];
+    float s = 0.0f;
+    const float scale = 2.0f / (float)n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = y[i] - t[i];
+        s += d * d;
+        const float gi = scale * d;
+        df[i] = gi;
+        db[i] = to_bf16(gi);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss, (part[0] + part[1] + part[2] + part[3]) / (float)n);
+}
+
+// db[c] = sum over the rows of dz[rows x cols] (row-major).
+__global__ void colsum_kernel(const float* __restrict__ dz, int64_t rows, int cols, float* __restrict__ db) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.0f;
+    for (int64_t r = 0; r < rows; ++r) s += dz[r * cols + c];
+    db[c] = s;
+}
+
+// One Adam update of every parameter; also refreshes the BF16 copy the GEMMs read.
+// c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, uint16_t* __restrict__ pb, int64_t n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+        p[i] = pi;
+        pb[i] = to_bf16(pi);
+    }
+}
+
+namespace {
+unsigned grid_for(int64_t n, int threads) {
+    const int64_t b = (n + threads - 1) / threads;
+    return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+}  // namespace
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM));
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_grad(const float* y, const float* t, int64_t n, float* df, uint16_t* db, float* loss,
+                            hipStream_t st) {
+    if (n <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, y, t, n, df, db, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* dz, int64_t rows, int cols, float* db, hipStream_t st) {
+    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, st, dz, rows, cols, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, uint16_t* pb, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t st) {
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, g, m, v, pb, n, lr, b1, b2, eps, c1,
+                       c2);
+    return hipGetLastError();
+}
+
+}  // namespace mlp
