@@ -213,6 +213,22 @@ int pic_set_particles(pic_handle* h, int species, const double* x, const float* 
  * field at t_n; arrays of n_cells + 1 values, NULL to skip. */
 int pic_get_fields(pic_handle* h, double* q_nodes, double* phi, float* e_nodes);
 
+/* Warm start: replace the initial load of a discharge that has not been stepped by one
+ * drawn from cycle-averaged profiles given on n_points >= 2 equally spaced points spanning
+ * [0, d] (both electrodes included), linear in between: electron and ion densities
+ * [m^-3, >= 0], mean electron energy [eV, >= 0] and ion flux [m^-2 s^-1, along +x].
+ * The periodic state does not depend on the initial state (Sec. 3, on initial values),
+ * so the load only changes how long the discharge takes to reach it.
+ * Species s gets N_s = round(integral n_s dx / W) particles (W the constant weight,
+ * Sec. 2.5), positions by inverting the cumulative integral of the density, electrons
+ * Maxwellian at k_B T_e = (2/3) <eps_e>(x), ions Maxwellian at the gas temperature with
+ * mean v_x = Gamma_i / n_i (0 where n_i = 0), ids 0 .. N_s - 1, Philox counters
+ * (k, 0, 0 and 1, (s << 8) | 0xFE).  Then deposits and solves the field at t = 0.
+ * Host arrays, copied; synchronises.  PIC_ESTATE if the discharge was stepped,
+ * PIC_ECAPACITY if N_s exceeds the capacity, PIC_EINVAL for bad profiles. */
+int pic_load_profiles(pic_handle* h, int32_t n_points, const double* n_e, const double* n_i,
+                      const double* mean_energy_e_eV, const double* flux_i);
+
 /* Record, for every collision test, the outcome per particle: 0 not a candidate,
  * 1 null collision, 2 + j table j selected.  Recording costs one byte per particle per
  * step and is off by default. */

@@ -22,7 +22,7 @@ EXPORTED = ("pic_init", "pic_step", "pic_sync", "pic_moments", "pic_free", "pic_
             "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
             "pic_batch_free", "pic_batch_last_error", "pic_batch_timing", "pic_batch_set_graph",
             "pic_batch_graph_launches", "pic_batch_autotune",
-            "mlp_init", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_gradient",
+            "pic_load_profiles", "mlp_init", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_gradient",
             "mlp_train_step", "mlp_free", "mlp_last_error")
 
 
@@ -127,6 +127,7 @@ def load_library(path: str = None):
         "pic_batch_set_graph": (C.c_int, [C.c_void_p, C.c_int64]),
         "pic_batch_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
         "pic_batch_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
+        "pic_load_profiles": (C.c_int, [H, C.c_int32, dp, dp, dp, dp]),
         "mlp_init": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
                                C.POINTER(C.c_void_p)]),
         "mlp_num_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -267,6 +268,15 @@ def pic_set_particles(h, species: int, x, vx, vy, vz, ids, next_id: int, step: i
     _check(h, load_library().pic_set_particles(h, species, _ptr(xd, C.c_double), *[_ptr(v, fp) for v in arrs],
                                                _ptr(ids, C.c_uint32),
                                                int(ids.size), int(next_id), int(step)))
+
+
+def pic_load_profiles(h, n_e, n_i, mean_energy_e, flux_i):
+    """Warm start of a discharge that has not been stepped, from profiles on equally spaced
+    points spanning the gap (see include/pic1d.h)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (n_e, n_i, mean_energy_e, flux_i)]
+    n = arrs[0].size
+    assert all(a.size == n for a in arrs)
+    _check(h, load_library().pic_load_profiles(h, n, *[_ptr(a, C.c_double) for a in arrs]))
 
 
 def pic_get_fields(h, n_nodes: int) -> dict:

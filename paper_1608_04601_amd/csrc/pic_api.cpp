@@ -18,6 +18,8 @@ namespace pic {
 hipError_t launch_pass(int mode, const Params& P, int blocks, int threads, size_t lds, hipStream_t st);
 hipError_t launch_load(const Params& P, int s, int64_t n, double vth, hipStream_t st);
 hipError_t launch_sort(const Params& P, unsigned* cnt, unsigned* cursor, int blocks, int threads, hipStream_t st);
+hipError_t launch_load_profile(const Params& P, int s, int64_t n, unsigned b, const double* tab, int np, double h_m,
+                               hipStream_t st);
 hipError_t launch_reset_window(const Params& P, hipStream_t st);
 hipError_t set_pass_lds_limit(size_t bytes);
 hipError_t pass_occupancy(int threads, size_t lds, int* blocks_per_cu);
@@ -746,6 +748,69 @@ int pic_set_particles(pic_handle* h, int species, const double* x, const float* 
     c.n_alive[species] = n;
     c.next_id[species] = next_id == 0 ? 0 : (int64_t)next_id;
     c.step = step;
+    if (!hip_ok(h, hipMemcpy(h->P.ctrl, &c, sizeof(c), hipMemcpyHostToDevice), "write ctrl")) return h->status;
+    if (!hip_ok(h, hipMemset(h->P.Qs, 0, 2 * (h->cfg.n_cells + 1) * sizeof(unsigned long long)), "zero Q"))
+        return h->status;
+    if (launch_pass_timed(h, pic::kDeposit)) return h->status;
+    return check_device(h);
+}
+
+int pic_load_profiles(pic_handle* h, int32_t n_points, const double* n_e, const double* n_i,
+                      const double* mean_energy_e_eV, const double* flux_i) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (n_points < 2 || n_points > 65536) return fail(h, PIC_EINVAL, "n_points must be in [2, 65536]");
+    if (!n_e || !n_i || !mean_energy_e_eV || !flux_i) return fail(h, PIC_EINVAL, "profile arrays are NULL");
+    for (int j = 0; j < n_points; ++j) {
+        if (!std::isfinite(n_e[j]) || !std::isfinite(n_i[j]) || !std::isfinite(mean_energy_e_eV[j]) ||
+            !std::isfinite(flux_i[j]))
+            return fail(h, PIC_EINVAL, "profiles must be finite");
+        if (n_e[j] < 0.0 || n_i[j] < 0.0 || mean_energy_e_eV[j] < 0.0)
+            return fail(h, PIC_EINVAL, "densities and the mean energy must be >= 0");
+    }
+    if (h->pending) return fail(h, PIC_ESTATE, "the discharge has already been stepped");
+    if (check_device(h)) return h->status;
+    pic::Ctrl c;
+    if (read_ctrl(h, &c)) return h->status;
+    if (c.step != 0) return fail(h, PIC_ESTATE, "the discharge has already been stepped");
+    // per species: cumulative integral, density, thermal speed squared, drift
+    const double hm = h->cfg.gap_m / (double)(n_points - 1);
+    const double kE0 = 1.602176634e-19, kKB = 1.380649e-23, kME = 9.1093837015e-31, kAMU = 1.66053906660e-27;
+    const double M = h->cfg.gas_mass_amu * kAMU;
+    std::vector<double> tab[2];
+    int64_t count[2];
+    for (int s = 0; s < 2; ++s) {
+        const double* dens = s == 0 ? n_e : n_i;
+        std::vector<double>& t = tab[s];
+        t.assign((size_t)4 * n_points, 0.0);
+        for (int j = 1; j < n_points; ++j) t[j] = t[j - 1] + 0.5 * (dens[j - 1] + dens[j]) * hm;
+        for (int j = 0; j < n_points; ++j) {
+            t[n_points + j] = dens[j];
+            t[2 * n_points + j] = s == 0 ? kE0 * (2.0 / 3.0) * mean_energy_e_eV[j] / kME
+                                         : kKB * h->cfg.gas_temperature_K / M;
+            t[3 * n_points + j] = (s == 1 && n_i[j] > 0.0) ? flux_i[j] / n_i[j] : 0.0;
+        }
+        count[s] = (int64_t)std::floor(t[n_points - 1] / h->W + 0.5);
+        if (count[s] < 1) return fail(h, PIC_EINVAL, "a density profile holds less than one particle");
+        if (count[s] > h->cfg.capacity[s]) return fail(h, PIC_ECAPACITY, "the profiles need more particles than capacity");
+    }
+    double* dtab = nullptr;
+    if (!hip_ok(h, hipMalloc(&dtab, sizeof(double) * 8 * (size_t)n_points), "hipMalloc")) return h->status;
+    const unsigned b = c.cur;
+    bool ok = true;
+    for (int s = 0; s < 2 && ok; ++s)
+        ok = hip_ok(h, hipMemcpyAsync(dtab + (size_t)4 * n_points * s, tab[s].data(), sizeof(double) * 4 * n_points,
+                                      hipMemcpyHostToDevice, h->stream), "copy profiles") &&
+             hip_ok(h, pic::launch_load_profile(h->P, s, count[s], b, dtab + (size_t)4 * n_points * s, n_points, hm,
+                                                h->stream), "load_profile_kernel");
+    ok = hip_ok(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize") && ok;
+    (void)hipFree(dtab);
+    if (!ok) return h->status;
+    for (int s = 0; s < 2; ++s) {
+        c.n_slots[s] = count[s];
+        c.n_alive[s] = count[s];
+        c.next_id[s] = count[s];
+    }
     if (!hip_ok(h, hipMemcpy(h->P.ctrl, &c, sizeof(c), hipMemcpyHostToDevice), "write ctrl")) return h->status;
     if (!hip_ok(h, hipMemset(h->P.Qs, 0, 2 * (h->cfg.n_cells + 1) * sizeof(unsigned long long)), "zero Q"))
         return h->status;

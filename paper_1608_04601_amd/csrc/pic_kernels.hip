@@ -51,7 +51,7 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return make_uint4(c0, c1, c2, c3);
 }
 
-enum Stream : uint32_t { kCollision = 0, kTarget = 1, kScatter = 2, kNewIon = 3, kLoad = 0xFF };
+enum Stream : uint32_t { kCollision = 0, kTarget = 1, kScatter = 2, kNewIon = 3, kWarm = 0xFE, kLoad = 0xFF };
 
 // u = ((w >> 9) + 1/2) 2^-23 in (0, 1); exact in FP32.
 __device__ __forceinline__ float u01(uint32_t w) { return ((float)(w >> 9) + 0.5f) * 0x1p-23f; }
@@ -1216,6 +1216,53 @@ __global__ void load_kernel(Params P, int s, int64_t n, double vth) {
     P.id[0][s][k] = (uint32_t)k;
 }
 
+// Warm-start load of species s from profiles on np equally spaced points spanning the gap
+// (linear in between): tab = [C | n | v2 | u], np entries each, with C the cumulative
+// integral of the density n (trapezoids of width h_m metres), v2 the thermal speed squared
+// per component and u the mean v_x.  Particle k inverts C at u01 * C[np - 1] (segment by
+// binary search, then the root of a t + (b - a) t^2 / 2 = (c - C_j) / h_m), takes a
+// Maxwellian velocity with v2 and u interpolated at its position, and id k.  Counters
+// (k, 0, 0 and 1, (s << 8) | kWarm).
+__global__ void load_profile_kernel(Params P, int s, int64_t n, unsigned b, const double* __restrict__ tab, int np,
+                                    double h_m) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t tag = ((uint32_t)s << 8) | kWarm;
+    const uint4 A = philox((uint32_t)k, 0u, 0u, tag, P.key0, P.key1);
+    const uint4 B = philox((uint32_t)k, 0u, 1u, tag, P.key0, P.key1);
+    const double* C = tab;
+    const double* dens = tab + np;
+    const double* v2 = tab + 2 * np;
+    const double* drift = tab + 3 * np;
+    const double c = u01d(A.x) * C[np - 1];
+    int lo = 0, hi = np - 1;   // the last j <= np - 2 with C[j] <= c
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (C[mid] <= c) lo = mid; else hi = mid;
+    }
+    const int j = lo;
+    const double a = dens[j], bb = dens[j + 1];
+    const double q = (c - C[j]) / h_m;
+    const double disc = sqrt(fmax(a * a + 2.0 * (bb - a) * q, 0.0));
+    double t = (a + disc > 0.0) ? 2.0 * q / (a + disc) : 0.5;
+    t = fmin(fmax(t, 0.0), 1.0);
+    float x = (float)(((double)j + t) * ((double)P.n_cells / (double)(np - 1)));
+    if (!(x < P.ncf)) x = nextafterf(P.ncf, 0.0f);
+    if (!(x > 0.0f)) x = 1.0e-30f;
+    const double vth = sqrt((1.0 - t) * v2[j] + t * v2[j + 1]);
+    const double um = (1.0 - t) * drift[j] + t * drift[j + 1];
+    const double r0 = sqrt(-2.0 * log(u01d(A.y)));
+    double s0, c0, s1, c1;
+    sincospi(2.0 * u01d(A.z), &s0, &c0);
+    const double r1 = sqrt(-2.0 * log(u01d(B.x)));
+    sincospi(2.0 * u01d(B.y), &s1, &c1);
+    P.x[b][s][k] = x;
+    P.vx[b][s][k] = (float)(vth * r0 * c0 + um);
+    P.vy[b][s][k] = (float)(vth * r0 * s0);
+    P.vz[b][s][k] = (float)(vth * r1 * c1);
+    P.id[b][s][k] = (uint32_t)k;
+}
+
 // ----------------------------------------------------------------------------------
 // Periodic reordering (performance only; results do not depend on the order because
 // every random number is keyed by particle id and the deposits are exact).  A species is
@@ -1577,6 +1624,16 @@ hipError_t launch_load(const Params& P, int s, int64_t n, double vth, hipStream_
     const int threads = 256;
     const int64_t blocks = (n + threads - 1) / threads;
     hipLaunchKernelGGL(load_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, P, s, n, vth);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_profile(const Params& P, int s, int64_t n, unsigned b, const double* tab, int np, double h_m,
+                               hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (np < 2 || b > 1u) return hipErrorInvalidValue;
+    const int threads = 256;
+    const int64_t blocks = (n + threads - 1) / threads;
+    hipLaunchKernelGGL(load_profile_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, P, s, n, b, tab, np, h_m);
     return hipGetLastError();
 }
 

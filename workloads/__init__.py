@@ -194,3 +194,36 @@ def sweep_argon(n_discharges: int = 64, seed: int = 0) -> Tuple[Discharge, ...]:
             n_super=(npart, npart), capacity=(8 * npart, 8 * npart), seed=seed * 1000 + k,
             processes=argon_like(top, top), sort_every=20, moments_every=1, max_births_per_step=1 << 18))
     return tuple(out)
+
+
+GAS_IDS = ("argon", "helium")
+
+
+def surrogate_params(n: int, seed: int) -> np.ndarray:
+    """Discharge parameters of the surrogate's training (seed 1) and held-out (seed 2)
+    draws from default_rng(seed): rows (p [Pa], V0 [V], d [m], gas id 0 argon / 1 helium),
+    p ~ U(10, 80), V0 ~ U(100, 400), d ~ U(0.02, 0.03), gas id ~ U{0, 1}."""
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(10.0, 80.0, n)
+    v0 = rng.uniform(100.0, 400.0, n)
+    d = rng.uniform(0.02, 0.03, n)
+    gas = rng.integers(0, 2, n).astype(np.float64)
+    return np.stack([p, v0, d, gas], axis=1)
+
+
+def surrogate_discharge(params, k: int = 0, seed: int = 0, n_super: int = 20_000, n_cells: int = 128,
+                        steps_per_period: int = 1000, capacity_factor: int = 40) -> Discharge:
+    """A discharge of the surrogate's family at reduced fidelity: 128 cells, dt = T_rf/1000,
+    2e4 particles per species at n_init = 1e15 m^-3 (this fixes the weight), uniform
+    Maxwellian start at 2 eV / 0.026 eV; storage for capacity_factor x the initial count,
+    since the periodic state's density can be many times n_init."""
+    p, v0, d, gas = (float(v) for v in params)
+    top = _table_top(v0)
+    helium = int(round(gas)) == 1
+    return Discharge(
+        name=f"{GAS_IDS[int(helium)]}_{p:.1f}Pa_{v0:.0f}V_{100 * d:.2f}cm_{k}", gap_m=d, pressure_Pa=p,
+        gas_temperature_K=300.0, gas_mass_amu=AMU_HE if helium else AMU_AR, rf_voltage_V=v0, rf_frequency_Hz=F_RF,
+        dt_s=1.0 / (F_RF * steps_per_period), n_cells=n_cells, n_init_m3=1e15, te_init_eV=2.0, ti_init_eV=0.026,
+        n_super=(n_super, n_super), capacity=(capacity_factor * n_super, capacity_factor * n_super),
+        seed=seed * 100_000 + k, processes=helium_like(top, top) if helium else argon_like(top, top),
+        sort_every=20, moments_every=1, max_births_per_step=1 << 18)
