@@ -174,12 +174,59 @@ def run_sweep(args, B, torch):
     print(json.dumps(out), flush=True)
 
 
+def run_warmstart(args, B, torch):
+    """RF periods to the periodic steady state, warm (surrogate) against cold (uniform)
+    start: the network is trained on the GPU from stored steady states of the batched PIC
+    (seed-1 parameter draws), then held-out draws (seed 2) run cold and warm in one batch
+    until the steady-state criterion holds (or the period limit)."""
+    import workloads as W
+    from paper_1608_04601_amd import warmstart as WS
+    torch.cuda.set_device(0)
+    data = np.load(WS.DATA_PATH)
+    keep = ~data["extinct"]
+    t0 = time.time()
+    net, norm, loss = WS.train(data["params"][keep], data["profiles"][keep], steps=4000)
+    train_s = time.time() - t0
+    params = W.surrogate_params(args.ws_n, 2)
+    t1 = time.time()
+    rows = WS.evaluate(net, norm, params, 2, args.ws_periods,
+                       log=lambda m: print(m, file=sys.stderr, flush=True))
+    eval_s = time.time() - t1
+    sm = WS.summarize(rows, args.ws_periods)
+    if args.ws_out:
+        with open(args.ws_out, "w") as f:
+            json.dump(dict(summary=sm, rows=rows), f, indent=1)
+    out = {
+        "metric": "RF cycles to steady state, warm vs cold",
+        "value": sm["warm_periods_mean"],
+        "unit": "RF periods (warm start, mean)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "cold_periods_mean": sm["cold_periods_mean"],
+        "reduction": (sm["cold_periods_mean"] / sm["warm_periods_mean"]) if sm["warm_periods_mean"] else None,
+        "vs_baseline": None,
+        "dtype": "f32 particles, bf16 network",
+        "data": "synthetic",
+        "config": {"workload": f"surrogate_heldout_{args.ws_n}", "training_steady_states": int(keep.sum()),
+                   "period_limit": args.ws_periods, "cells": 128, "steps_per_rf_period": 1000,
+                   "particles_per_species_initial": 20000},
+        "summary": sm,
+        "train_s": train_s,
+        "train_loss": loss,
+        "evaluate_s": eval_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="production", choices=sorted(workloads_by_name()))
+    ap.add_argument("--workload", default="production", choices=sorted(workloads_by_name()) + ["warmstart"])
+    ap.add_argument("--ws-n", type=int, default=16, help="warmstart: held-out discharges")
+    ap.add_argument("--ws-periods", type=int, default=1500, help="warmstart: RF period limit")
+    ap.add_argument("--ws-out", default=None, help="warmstart: write every discharge's result (JSON)")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps of the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-blocks", type=int, default=0)
@@ -207,6 +254,9 @@ def main():
     import torch
     from paper_1608_04601_amd import binding as B
 
+    if args.workload == "warmstart":
+        run_warmstart(args, B, torch)
+        return
     if args.workload == "sweep":
         run_sweep(args, B, torch)
         return

@@ -1,0 +1,78 @@
+"""Host logic of the warm start (no GPU): the steady-state criterion on synthetic period
+sequences, and the network's input/output encoding."""
+import numpy as np
+
+from paper_1608_04601_amd import warmstart as WS
+
+
+def _prof(level, rng=None, noise=0.0):
+    z = np.linspace(0.0, 1.0, WS.N_POINTS)
+    base = np.array([np.sin(np.pi * z) + 0.1, np.sin(np.pi * z) + 0.2, 3.0 + z, 100.0 * z, z - 0.5])
+    p = base * level
+    if rng is not None:
+        p = p * (1.0 + noise * rng.normal(size=p.shape))
+    return p
+
+
+def test_exponential_relaxation_is_detected_when_the_windows_agree():
+    rng = np.random.default_rng(0)
+    tau = 50.0
+    det = WS.SteadyState()
+    for c in range(1000):
+        level = 2.0 - np.exp(-c / tau)
+        det.add(_prof(level, rng, 1e-3), created=1000.0, absorbed=1000.0 * (1.0 + 0.001 * rng.normal()))
+        if det.done():
+            break
+    # two consecutive 20-period means differ by < 1 % once 20 tau' e^{-c/tau} / level < 1 %
+    # (a relative change of ~ (20/tau) e^{-c/tau} / 2); that happens near c = tau ln(20) ~ 150
+    assert det.steady_at is not None and 120 <= det.steady_at <= 200, det.steady_at
+    assert det.done() and det.periods == det.steady_at + det.W
+
+
+def test_ion_balance_blocks_detection():
+    det = WS.SteadyState()
+    for c in range(200):
+        det.add(_prof(1.0), created=1000.0, absorbed=1050.0)   # 5 % imbalance
+    assert det.steady_at is None
+    det2 = WS.SteadyState()
+    for c in range(200):
+        det2.add(_prof(1.0), created=1000.0, absorbed=1020.0)  # 2 %: inside 3 %
+    assert det2.steady_at == 40
+
+
+def test_no_decision_before_two_windows():
+    det = WS.SteadyState()
+    for c in range(39):
+        assert not det.add(_prof(1.0), 10.0, 10.0)
+    assert det.add(_prof(1.0), 10.0, 10.0)
+
+
+def test_a_drifting_quantity_blocks_detection():
+    det = WS.SteadyState()
+    for c in range(300):
+        p = _prof(1.0)
+        p[4] += 0.002 * c   # flux keeps drifting: the window means differ by 4e-2 of its max
+        det.add(p, 10.0, 10.0)
+    assert det.steady_at is None
+
+
+def test_encoding_round_trip():
+    rng = np.random.default_rng(1)
+    params = np.stack([rng.uniform(10, 80, 5), rng.uniform(100, 400, 5), rng.uniform(0.02, 0.03, 5),
+                       rng.integers(0, 2, 5)], axis=1).astype(float)
+    X = WS.encode_inputs(params)
+    assert X.shape == (5, 4) and np.all(np.abs(X) <= 1.0 + 1e-6)
+    prof = np.abs(rng.normal(size=(5, 5, WS.N_POINTS))) * np.array([1e16, 1e16, 3, 100, 1e19])[None, :, None]
+    prof[:, 0, 0] = 0.0   # below the density floor
+    back = WS.from_targets(params, WS.to_targets(params, prof))
+    expect = prof.copy()
+    expect[:, 0, 0] = WS.DENSITY_FLOOR
+    np.testing.assert_allclose(back, expect, rtol=1e-12, atol=0)
+
+
+def test_profile_change_is_relative_rms():
+    a = np.ones((5, 10))
+    b = a.copy()
+    b[2] *= 1.05
+    ch = WS.profile_change(a, b)
+    np.testing.assert_allclose(ch, [0, 0, 0.05 / 1.05, 0, 0], rtol=1e-12)
