@@ -104,6 +104,10 @@ class Oracle:
         self.violations = np.zeros(2, dtype=np.int64)
         self.absorbed_total = np.zeros((2, 2), dtype=np.int64)
         self.J = 0.0
+        # RF amplitude; with a target current amplitude J0 it is adapted once per whole RF
+        # period as V0 <- V0 J0 / J_calc, J_calc the period's max |J| (Sec. 2, Eq.
+        # "adaptivevoltage"), otherwise it stays the prescribed value
+        self.V0 = float(cfg.rf_voltage_V)
         self.last = {}
         if load:
             self._load()
@@ -153,7 +157,7 @@ class Oracle:
         """Deposit, solve with phi_0 = V0 sin(2 pi f t_step), form E (Sec. 2, 2.2)."""
         cfg, d = self.cfg, self.d
         self.Q = self._charge()
-        phi0 = cfg.rf_voltage_V * np.sin(2.0 * np.pi * cfg.rf_frequency_Hz * step * cfg.dt_s)
+        phi0 = self.V0 * np.sin(2.0 * np.pi * cfg.rf_frequency_Hz * step * cfg.dt_s)
         self.phi = field.solve_poisson(self.Q, d.dx, phi0, 0.0)
         self.E = field.node_field(self.phi, self.Q, d.dx)
         self.sigma0 = EPS0 * self.E[0]
@@ -324,6 +328,9 @@ class Oracle:
             if self.period_valid:
                 self.J_max_sum += self.J_period_max
                 self.n_periods += 1
+                j0 = getattr(cfg, "j0_target_A_m2", 0.0)
+                if j0 > 0.0 and self.J_period_max > 0.0:
+                    self.V0 *= j0 / self.J_period_max
             self.J_period_max = 0.0
             self.period_valid = True
         if self.n % cfg.moments_every != 0:

@@ -76,6 +76,7 @@ class Discharge:
     moments_every: int = 1
     max_births_per_step: int = 65536
     electron_order: int = -1   # periodic electron reordering: 1 by cell, 0 compaction only, -1 automatic
+    j0_target_A_m2: float = 0.0   # > 0: V0 is adapted every RF period towards this current amplitude
 
     @property
     def steps_per_period(self) -> int:
