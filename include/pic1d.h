@@ -106,6 +106,10 @@ typedef struct pic_config {
                                    sort interval.  Ions are always sorted by cell.  Results do
                                    not depend on this choice. */
     int32_t reserved;           /* must be 0                                           */
+    double j0_target_A_m2;      /* 0: V0 stays rf_voltage_V.  > 0: current-driven operation
+                                   (Sec. 2, Eq. "adaptivevoltage"): at the end of every whole RF
+                                   period the amplitude becomes V0 J0 / J_calc, J_calc the
+                                   period's max |J|; finite, >= 0 */
 } pic_config;
 
 /* Window averages since the last reset (pic_moments).  Arrays are caller-owned host
@@ -143,6 +147,7 @@ typedef struct pic_counters {
     double J_last_A_m2;              /* J^{n-1/2} of the last step (Sec. 2.2)            */
     double sigma0_C_m2;              /* surface charge eps0 E(0) on the powered electrode */
     double sigmad_C_m2;              /* surface charge -eps0 E(d) on the grounded one     */
+    double V0_V;                     /* RF amplitude in use (changes only when current-driven) */
 } pic_counters;
 
 /* Constants the library derived from the configuration (pic_get_derived). */

@@ -51,7 +51,7 @@ class pic_config(C.Structure):
                 ("xsec", C.POINTER(pic_xsec)), ("n_init_super", C.c_int64 * 2), ("capacity", C.c_int64 * 2),
                 ("seed", C.c_uint64), ("sort_every", C.c_int32), ("moments_every", C.c_int32),
                 ("max_births_per_step", C.c_int32), ("launch_blocks", C.c_int32),
-                ("electron_order", C.c_int32), ("reserved", C.c_int32)]
+                ("electron_order", C.c_int32), ("reserved", C.c_int32), ("j0_target_A_m2", C.c_double)]
 
 
 class pic_moments_out(C.Structure):
@@ -68,7 +68,8 @@ class pic_counters(C.Structure):
                 ("next_id", C.c_int64 * 2), ("particle_steps", C.c_int64),
                 ("absorbed_total", (C.c_int64 * 2) * 2), ("collisions", C.c_int64 * MAX_PROCESSES),
                 ("numax_violations", C.c_int64 * 2), ("births_total", C.c_int64),
-                ("J_last_A_m2", C.c_double), ("sigma0_C_m2", C.c_double), ("sigmad_C_m2", C.c_double)]
+                ("J_last_A_m2", C.c_double), ("sigma0_C_m2", C.c_double), ("sigmad_C_m2", C.c_double),
+                ("V0_V", C.c_double)]
 
 
 class pic_derived(C.Structure):
@@ -182,6 +183,7 @@ class Config:
         c.sort_every, c.moments_every = int(disc.sort_every), int(disc.moments_every)
         c.max_births_per_step, c.launch_blocks = int(disc.max_births_per_step), int(launch_blocks)
         c.electron_order, c.reserved = int(getattr(disc, "electron_order", -1)), 0
+        c.j0_target_A_m2 = float(getattr(disc, "j0_target_A_m2", 0.0))
         self.c = c
 
 
@@ -235,7 +237,8 @@ def pic_get_counters(h) -> dict:
                 particle_steps=c.particle_steps,
                 absorbed_total=np.array([[c.absorbed_total[s][e] for e in range(2)] for s in range(2)]),
                 collisions=np.array(list(c.collisions)), numax_violations=tuple(c.numax_violations),
-                births_total=c.births_total, J_last=c.J_last_A_m2, sigma0=c.sigma0_C_m2, sigmad=c.sigmad_C_m2)
+                births_total=c.births_total, J_last=c.J_last_A_m2, sigma0=c.sigma0_C_m2, sigmad=c.sigmad_C_m2,
+                V0=c.V0_V)
 
 
 def pic_get_derived(h) -> dict:

@@ -249,6 +249,7 @@ std::string validate(const pic_config* c) {
     if (c->launch_blocks < 0 || c->launch_blocks > 65536) return "launch_blocks must be in [0, 65536]";
     if (c->electron_order < -1 || c->electron_order > 1) return "electron_order must be -1, 0 or 1";
     if (c->reserved != 0) return "reserved must be 0";
+    if (!std::isfinite(c->j0_target_A_m2) || c->j0_target_A_m2 < 0.0) return "j0_target_A_m2 must be finite and >= 0";
     int per_species[2] = {0, 0};
     for (int j = 0; j < c->n_xsec; ++j) {
         const pic_xsec& p = c->xsec[j];
@@ -477,6 +478,7 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         P.eps0 = kEps0;
         P.e0W = kE0 * h->W;
         P.V0 = c.rf_voltage_V;
+        P.J0_target = c.j0_target_A_m2;
         P.omega = 2.0 * kPi * c.rf_frequency_Hz;
         P.dt_d = c.dt_s;
         // periodic reordering: ions by cell; electrons by cell only while they stay near
@@ -531,6 +533,7 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
         }
         c0.period_valid = 1;
         c0.cost_ratio = 1.0;
+        c0.V0 = c.rf_voltage_V;
         if (!hip_ok(h, hipMemcpyAsync(P.ctrl, &c0, sizeof(c0), hipMemcpyHostToDevice, h->stream), "upload ctrl") ||
             !hip_ok(h, hipMemsetAsync(P.Qs, 0, 2 * nn * sizeof(unsigned long long), h->stream), "zero Q") ||
             !hip_ok(h, hipMemsetAsync(P.rep, 0, pic::kRepSets * pic::kRepStride * sizeof(unsigned long long), h->stream),
@@ -653,6 +656,7 @@ int pic_get_counters(pic_handle* h, pic_counters* out) {
     out->J_last_A_m2 = c.J_last;
     out->sigma0_C_m2 = c.sigma0;
     out->sigmad_C_m2 = c.sigmad;
+    out->V0_V = c.V0;
     return PIC_OK;
 }
 

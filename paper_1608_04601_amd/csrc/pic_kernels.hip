@@ -995,7 +995,7 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
     if (kSolve) {
         double E0, EN;
         const double t1 = (double)(step + ((MODE & kAdvance) ? 1 : 0)) * P.dt_d;
-        solve_field(P, Qd, phis, scratch, P.V0 * sin(P.omega * t1), E0, EN);
+        solve_field(P, Qd, phis, scratch, cs->V0 * sin(P.omega * t1), E0, EN);
         // the step just started is sampled at its completion: densities at x^{n+1} are
         // this launch's deposit, and phi^{n+1} was just solved for
         const bool next_sampled = (MODE & kAdvance) && ((step + 1) % P.moments_every == 0);
@@ -1031,6 +1031,10 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
                     if (cs->period_valid) {
                         cs->J_max_sum += cs->J_period_max;
                         cs->n_periods += 1;
+                        // current-driven operation (Sec. 2, Eq. "adaptivevoltage"): the next
+                        // period runs at V0 J0 / J_calc, J_calc this period's max |J|
+                        if (P.J0_target > 0.0 && cs->J_period_max > 0.0)
+                            cs->V0 *= P.J0_target / cs->J_period_max;
                     }
                     cs->J_period_max = 0.0;
                     cs->period_valid = 1;

@@ -83,6 +83,7 @@ struct Ctrl {
     unsigned long long cost_ticks[2];  // workgroup time spent per species in the running launch
     unsigned long long cost_parts[2];  // and the slots it covered
     double cost_ratio;                 // smoothed time per electron slot / time per ion slot
+    double V0;                         // RF amplitude in use [V]
 };
 
 struct ProcDev {
@@ -145,7 +146,8 @@ struct Params {
     double dx_d;
     double eps0;
     double e0W;               // e0 * W: node charge per unit of deposited weight
-    double V0, omega, dt_d;
+    double V0, omega, dt_d;   // V0: the configured amplitude (the one in use is Ctrl::V0)
+    double J0_target;         // > 0: current-driven, V0 adapted once per RF period
 };
 
 }  // namespace pic
