@@ -259,12 +259,14 @@ def load_net(path, stream=None):
     return net, dict(mu=w["mu"], sd=w["sd"])
 
 
-def evaluate(net, norm, params, seed, max_periods, log=None):
-    """Cold and warm runs of the same held-out discharges in one batch."""
+def evaluate(net, norm, params, seed, max_periods, log=None, index=None):
+    """Cold and warm runs of the same held-out discharges in one batch; index[k] (default k)
+    is discharge k's position in its draw, which keys its random numbers."""
     import workloads as W
     K = len(params)
     pred = predict(net, norm, params)
-    discs = [W.surrogate_discharge(params[k], k, seed=seed) for k in range(K)]
+    index = list(range(K)) if index is None else list(index)
+    discs = [W.surrogate_discharge(params[k], index[k], seed=seed) for k in range(K)]
     warm = [None] * K + [warm_profiles(pred[k]) for k in range(K)]
     res = run(discs + discs, max_periods, warm=warm, log=log)
     rows = []
