@@ -179,6 +179,8 @@ def run_warmstart(args, B, torch):
     start: the network is trained on the GPU from stored steady states of the batched PIC
     (seed-1 parameter draws), then held-out draws (seed 2) run cold and warm in one batch
     until the steady-state criterion holds (or the period limit)."""
+    import numpy as np
+
     import workloads as W
     from paper_1608_04601_amd import warmstart as WS
     torch.cuda.set_device(0)
@@ -218,12 +220,58 @@ def run_warmstart(args, B, torch):
     print(json.dumps(out), flush=True)
 
 
+def run_mlp(args, B, torch):
+    """Throughput of the surrogate network's kernels (BF16 MFMA GEMMs with fused epilogues):
+    the forward pass of 65536 samples and a training step (forward, reverse pass, Adam) on
+    8192 samples, 4 -> 3 x 256 -> 640, timed with torch events on the library's stream."""
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    dims = [4, 256, 256, 256, 640]
+    flop_fwd = 2.0 * sum(dims[i] * dims[i + 1] for i in range(4))   # per sample
+    res = {}
+    for name, batch, reps in (("forward", 65536, 20), ("train_step", 8192, 20)):
+        net = B.Mlp(4, 256, 3, 640, max_batch=batch, seed=1, stream=stream.cuda_stream)
+        x = torch.rand(batch, 4, device="cuda") * 2 - 1
+        t = torch.rand(batch, 640, device="cuda")
+        y = torch.empty(batch, 640, device="cuda")
+        run = (lambda: net.forward(x, y)) if name == "forward" else (lambda: net.train_step(x, t, 1e-4))
+        for _ in range(3):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        flop = flop_fwd * batch * (1 if name == "forward" else 3)   # backward: two GEMMs per layer
+        res[name] = {"batch": batch, "ms": ms, "TFLOP_s": flop / (ms * 1e-3) / 1e12}
+        net.close()
+    peak = 2500.0
+    out = {
+        "metric": "surrogate network throughput (BF16 MFMA, FP32 accumulate)",
+        "value": res["forward"]["TFLOP_s"],
+        "unit": "TFLOP/s (forward)",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "mlp_4x256x3x640", "flop_per_sample_forward": flop_fwd},
+        "roofline": {"bound": "mfma", "achieved": res["forward"]["TFLOP_s"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": res["forward"]["TFLOP_s"] / peak},
+        "train_step": res["train_step"],
+        "forward": res["forward"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="production", choices=sorted(workloads_by_name()) + ["warmstart"])
+    ap.add_argument("--workload", default="production", choices=sorted(workloads_by_name()) + ["warmstart", "mlp"])
     ap.add_argument("--ws-n", type=int, default=16, help="warmstart: held-out discharges")
     ap.add_argument("--ws-periods", type=int, default=1500, help="warmstart: RF period limit")
     ap.add_argument("--ws-out", default=None, help="warmstart: write every discharge's result (JSON)")
@@ -256,6 +304,9 @@ def main():
 
     if args.workload == "warmstart":
         run_warmstart(args, B, torch)
+        return
+    if args.workload == "mlp":
+        run_mlp(args, B, torch)
         return
     if args.workload == "sweep":
         run_sweep(args, B, torch)

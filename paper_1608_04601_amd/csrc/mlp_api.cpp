@@ -30,6 +30,7 @@ struct mlp_handle {
     float* dzf[2] = {nullptr, nullptr};      // FP32 and BF16 dL/dz, ping-pong
     uint16_t* dzb[2] = {nullptr, nullptr};
     float* loss = nullptr;
+    float* part = nullptr;   // column-sum partials [kColPartsHost x max(width, n_out)]
     int64_t t = 0;   // Adam steps taken
     int status = PIC_OK;
     std::string err;
@@ -128,7 +129,7 @@ int backward(mlp_handle* h, const float* t, int64_t batch) {
         gw.Cf = h->g + h->w_off[l];
         gw.ldc = i;
         if (!mok(h, mlp::launch_gemm(gw, h->stream), "gemm launch") ||
-            !mok(h, mlp::launch_colsum(h->dzf[cur], batch, o, h->g + h->b_off[l], h->stream), "colsum launch"))
+            !mok(h, mlp::launch_colsum(h->dzf[cur], batch, o, h->part, h->g + h->b_off[l], h->stream), "colsum launch"))
             return h->status;
         if (l == 0) break;
         // dz_{l-1}[B x i] = (dz [B x o] . W_l [o x i]) masked where act[l] (relu output) > 0
@@ -190,7 +191,8 @@ int mlp_init(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, int32_t 
     const int64_t P = h->n_params;
     const int dmax = std::max(width, std::max(n_out, n_in));
     bool ok = alloc(h, &h->p, P) && alloc(h, &h->pb, P) && alloc(h, &h->g, P) && alloc(h, &h->m, P) &&
-              alloc(h, &h->v, P) && alloc(h, &h->y, (int64_t)max_batch * n_out) && alloc(h, &h->loss, 1);
+              alloc(h, &h->v, P) && alloc(h, &h->y, (int64_t)max_batch * n_out) && alloc(h, &h->loss, 1) &&
+              alloc(h, &h->part, (int64_t)mlp::kColPartsHost * dmax);
     for (int q = 0; ok && q < 2; ++q)
         ok = alloc(h, &h->dzf[q], (int64_t)max_batch * dmax) && alloc(h, &h->dzb[q], (int64_t)max_batch * dmax);
     h->act.assign(depth + 1, nullptr);

@@ -44,15 +44,48 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = 0; k0 < g.K; k0 += kBK) {
-        for (int e = tid; e < kBM * kBK; e += 256) {
-            const int r = e / kBK, c = e % kBK;
+        // Stage the 64 x 32 tiles: 16-byte loads of 8 operands where a tile row (or column)
+        // is contiguous in memory and 8-aligned (one load per thread per tile), else one
+        // element at a time.  Out-of-range operands are zero.
+        if (g.vec_a == 1) {   // contiguous along k
+            const int r = tid >> 2, c = (tid & 3) * 8;
             const int64_t m = m0 + r, k = k0 + c;
-            As[r * kLDK + c] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (uint16_t)0;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (m < g.M && k < g.K) v = *reinterpret_cast<const uint4*>(g.A + m * g.sam + k);
+            *reinterpret_cast<uint4*>(&As[r * kLDK + c]) = v;
+        } else if (g.vec_a == 2) {   // contiguous along m
+            const int c = tid >> 3, r = (tid & 7) * 8;
+            const int64_t m = m0 + r, k = k0 + c;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (m < g.M && k < g.K) v = *reinterpret_cast<const uint4*>(g.A + m + k * g.sak);
+            const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+            for (int j = 0; j < 8; ++j) As[(r + j) * kLDK + c] = h[j];
+        } else {
+            for (int e = tid; e < kBM * kBK; e += 256) {
+                const int r = e / kBK, c = e % kBK;
+                const int64_t m = m0 + r, k = k0 + c;
+                As[r * kLDK + c] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (uint16_t)0;
+            }
         }
-        for (int e = tid; e < kBN * kBK; e += 256) {
-            const int r = e / kBK, c = e % kBK;
+        if (g.vec_b == 1) {   // contiguous along k
+            const int r = tid >> 2, c = (tid & 3) * 8;
             const int64_t n = n0 + r, k = k0 + c;
-            Bs[r * kLDK + c] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (uint16_t)0;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (n < g.N && k < g.K) v = *reinterpret_cast<const uint4*>(g.B + k + n * g.sbn);
+            *reinterpret_cast<uint4*>(&Bs[r * kLDK + c]) = v;
+        } else if (g.vec_b == 2) {   // contiguous along n
+            const int c = tid >> 3, r = (tid & 7) * 8;
+            const int64_t n = n0 + r, k = k0 + c;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (n < g.N && k < g.K) v = *reinterpret_cast<const uint4*>(g.B + k * g.sbk + n);
+            const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+            for (int j = 0; j < 8; ++j) Bs[(r + j) * kLDK + c] = h[j];
+        } else {
+            for (int e = tid; e < kBN * kBK; e += 256) {
+                const int r = e / kBK, c = e % kBK;
+                const int64_t n = n0 + r, k = k0 + c;
+                Bs[r * kLDK + c] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (uint16_t)0;
+            }
         }
         __syncthreads();
         bf16x8 a[2], b[2];
@@ -110,12 +143,32 @@ __global__ void __launch_bounds__(256) loss_grad_kernel(const float* __restrict_
     if (threadIdx.x == 0) atomicAdd(loss, (part[0] + part[1] + part[2] + part[3]) / (float)n);
 }
 
-// db[c] = sum over the rows of dz[rows x cols] (row-major).
-__global__ void colsum_kernel(const float* __restrict__ dz, int64_t rows, int cols, float* __restrict__ db) {
+// Column sums db[c] = sum_r dz[r, c] of a row-major [rows x cols] matrix in two
+// deterministic passes: workgroup (x, y) sums 64 columns over its share of the rows (four
+// row lanes per column, combined in LDS) into part[y][c]; then each column adds its
+// kColParts partial sums in order.
+constexpr int kColParts = kColPartsHost;
+
+__global__ void __launch_bounds__(256) colsum_part_kernel(const float* __restrict__ dz, int64_t rows, int cols,
+                                                          float* __restrict__ part) {
+    __shared__ float red[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + tx;
+    const int64_t per = (rows + kColParts - 1) / kColParts;
+    const int64_t r0 = (int64_t)blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
+    float s = 0.0f;
+    if (c < cols)
+        for (int64_t r = r0 + ty; r < r1; r += 4) s += dz[r * cols + c];
+    red[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && c < cols) part[(int64_t)blockIdx.y * cols + c] = red[0][tx] + red[1][tx] + red[2][tx] + red[3][tx];
+}
+
+__global__ void colsum_final_kernel(const float* __restrict__ part, int cols, float* __restrict__ db) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cols) return;
     float s = 0.0f;
-    for (int64_t r = 0; r < rows; ++r) s += dz[r * cols + c];
+    for (int q = 0; q < kColParts; ++q) s += part[(int64_t)q * cols + c];
     db[c] = s;
 }
 
@@ -143,8 +196,19 @@ unsigned grid_for(int64_t n, int threads) {
 }
 }  // namespace
 
-hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
-    if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
+hipError_t launch_gemm(const GemmArgs& g0, hipStream_t st) {
+    if (g0.M <= 0 || g0.N <= 0 || g0.K <= 0) return hipErrorInvalidValue;
+    GemmArgs g = g0;
+    // vector staging needs 8-aligned starts of every 8-operand chunk and whole chunks in or
+    // out of range: the contiguous extent a multiple of 8, the other stride too, 16-byte
+    // aligned base
+    auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    g.vec_a = 0;
+    if (aligned(g.A) && g.sak == 1 && g.K % 8 == 0 && g.sam % 8 == 0) g.vec_a = 1;
+    else if (aligned(g.A) && g.sam == 1 && g.M % 8 == 0 && g.sak % 8 == 0) g.vec_a = 2;
+    g.vec_b = 0;
+    if (aligned(g.B) && g.sbk == 1 && g.K % 8 == 0 && g.sbn % 8 == 0) g.vec_b = 1;
+    else if (aligned(g.B) && g.sbn == 1 && g.N % 8 == 0 && g.sbk % 8 == 0) g.vec_b = 2;
     const dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM));
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, g);
     return hipGetLastError();
@@ -169,8 +233,12 @@ hipError_t launch_loss_grad(const float* y, const float* t, int64_t n, float* df
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float* dz, int64_t rows, int cols, float* db, hipStream_t st) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, st, dz, rows, cols, db);
+hipError_t launch_colsum(const float* dz, int64_t rows, int cols, float* part, float* db, hipStream_t st) {
+    hipLaunchKernelGGL(colsum_part_kernel, dim3((unsigned)((cols + 63) / 64), kColParts), dim3(256), 0, st, dz, rows,
+                       cols, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, st, part, cols, db);
     return hipGetLastError();
 }
 
