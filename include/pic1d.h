@@ -234,6 +234,53 @@ int pic_get_fields(pic_handle* h, double* q_nodes, double* phi, float* e_nodes);
 int pic_load_profiles(pic_handle* h, int32_t n_points, const double* n_e, const double* n_i,
                       const double* mean_energy_e_eV, const double* flux_i);
 
+/* ---- Diagnostics of the results section (off the particle pass).  A diagnostic window
+ * adds up samples of the completed electron state at chosen time levels: call
+ * pic_diag_sample every k steps for time averages, or once per RF period at a fixed phase
+ * (the paper's t f = 0.25) for phase-resolved profiles.  Per node (cloud-in-cell weights,
+ * node volume dx, dx/2 at the electrodes, constant weight W, averaged over the samples):
+ * n_e; U_e = w_e / n_e; the electron particle flux Gamma_e = sum v_x and energy flux
+ * Q_e = sum e0 U v_x; the ionisation rate S = sum n_gas sigma_iz(U) |v| (the expected rate
+ * of each electron on the ionisation tables); the density of fast electrons, U > |V0| / 4
+ * with the amplitude in use; the heating rate -e0 E Gamma_e formed per sample; the field.
+ * And the time and space averaged isotropic distribution f0(U)/n_e at the centres of
+ * n_bins energy bins over [0, u_max): count_k / (N dU sqrt(U_k)) with N every sampled
+ * electron, so that the integral of f0 sqrt(U) dU over all energies is n_e. */
+typedef struct pic_diag_out {
+    int32_t n_nodes;              /* in: n_cells + 1                                     */
+    int32_t n_bins;               /* in: the configured bin count (when eedf is set)     */
+    double* n_e_m3;               /* caller-owned [n_nodes] arrays, or NULL to skip      */
+    double* mean_energy_e_eV;     /* NaN where no electron was sampled                   */
+    double* flux_e_m2s;
+    double* energy_flux_e_W_m2;
+    double* ionisation_rate_m3s;
+    double* n_fast_m3;
+    double* heating_W_m3;
+    double* E_V_m;
+    double* eedf_eV_m32;          /* [n_bins] f0/n_e at the bin centres [eV^-3/2]        */
+    int64_t n_samples;            /* out */
+    int64_t n_electrons;          /* out: electrons summed over the samples              */
+    double u_max_eV;              /* out */
+} pic_diag_out;
+
+/* Allocate (first call) and clear the diagnostic window with n_bins in [1, 4096] energy
+ * bins over [0, u_max_eV).  6 (n_cells + 1) + n_bins words must fit 160 KiB of LDS. */
+int pic_diag_config(pic_handle* h, int32_t n_bins, double u_max_eV);
+
+/* Complete the pending step (as pic_sync does, without waiting) and add the state at the
+ * current time level to the window; enqueued.  PIC_ESTATE before pic_diag_config. */
+int pic_diag_sample(pic_handle* h);
+
+/* Averages over the window's samples into *out (synchronises); reset clears the window. */
+int pic_diag_read(pic_handle* h, pic_diag_out* out, int reset);
+
+/* Electron and ion particle fluxes into the powered electrode (z = 0) against time over
+ * the last RF period [m^-2 s^-1]: entry k is W N_k / dt with N_k the particles absorbed
+ * there during the step that started at phase k / n of the period, from the most recent
+ * period that reached that phase (recorded by every step).  n must be the steps per RF
+ * period (pic_get_derived).  Synchronises. */
+int pic_electrode_fluxes(pic_handle* h, int32_t n, double* gamma_e, double* gamma_i);
+
 /* Record, for every collision test, the outcome per particle: 0 not a candidate,
  * 1 null collision, 2 + j table j selected.  Recording costs one byte per particle per
  * step and is off by default. */

@@ -22,8 +22,22 @@ EXPORTED = ("pic_init", "pic_step", "pic_sync", "pic_moments", "pic_free", "pic_
             "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
             "pic_batch_free", "pic_batch_last_error", "pic_batch_timing", "pic_batch_set_graph",
             "pic_batch_graph_launches", "pic_batch_autotune",
-            "pic_load_profiles", "mlp_init", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_gradient",
+            "pic_load_profiles", "pic_diag_config", "pic_diag_sample", "pic_diag_read", "pic_electrode_fluxes",
+            "mlp_init", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_gradient",
             "mlp_train_step", "mlp_free", "mlp_last_error")
+
+
+class pic_diag_out(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_bins", C.c_int32)] + \
+        [(k, C.POINTER(C.c_double)) for k in ("n_e_m3", "mean_energy_e_eV", "flux_e_m2s", "energy_flux_e_W_m2",
+                                              "ionisation_rate_m3s", "n_fast_m3", "heating_W_m3", "E_V_m",
+                                              "eedf_eV_m32")] + \
+        [("n_samples", C.c_int64), ("n_electrons", C.c_int64), ("u_max_eV", C.c_double)]
+
+
+DIAG_KEYS = (("n_e", "n_e_m3"), ("mean_energy_e", "mean_energy_e_eV"), ("flux_e", "flux_e_m2s"),
+             ("energy_flux_e", "energy_flux_e_W_m2"), ("ionisation_rate", "ionisation_rate_m3s"),
+             ("n_fast", "n_fast_m3"), ("heating", "heating_W_m3"), ("E", "E_V_m"))
 
 
 class pic_tuning(C.Structure):
@@ -129,6 +143,10 @@ def load_library(path: str = None):
         "pic_batch_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
         "pic_batch_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
         "pic_load_profiles": (C.c_int, [H, C.c_int32, dp, dp, dp, dp]),
+        "pic_diag_config": (C.c_int, [H, C.c_int32, C.c_double]),
+        "pic_diag_sample": (C.c_int, [H]),
+        "pic_diag_read": (C.c_int, [H, C.POINTER(pic_diag_out), C.c_int]),
+        "pic_electrode_fluxes": (C.c_int, [H, C.c_int32, dp, dp]),
         "mlp_init": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
                                C.POINTER(C.c_void_p)]),
         "mlp_num_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -280,6 +298,33 @@ def pic_load_profiles(h, n_e, n_i, mean_energy_e, flux_i):
     n = arrs[0].size
     assert all(a.size == n for a in arrs)
     _check(h, load_library().pic_load_profiles(h, n, *[_ptr(a, C.c_double) for a in arrs]))
+
+
+def pic_diag_config(h, n_bins: int, u_max_eV: float):
+    _check(h, load_library().pic_diag_config(h, int(n_bins), float(u_max_eV)))
+
+
+def pic_diag_sample(h):
+    _check(h, load_library().pic_diag_sample(h))
+
+
+def pic_diag_read(h, n_nodes: int, n_bins: int, reset: bool = False) -> dict:
+    out = pic_diag_out()
+    out.n_nodes, out.n_bins = n_nodes, n_bins
+    arrs = {k: np.empty(n_nodes) for k, _ in DIAG_KEYS}
+    for k, f in DIAG_KEYS:
+        setattr(out, f, _ptr(arrs[k], C.c_double))
+    arrs["eedf"] = np.empty(n_bins)
+    out.eedf_eV_m32 = _ptr(arrs["eedf"], C.c_double)
+    _check(h, load_library().pic_diag_read(h, C.byref(out), 1 if reset else 0))
+    arrs.update(n_samples=out.n_samples, n_electrons=out.n_electrons, u_max=out.u_max_eV)
+    return arrs
+
+
+def pic_electrode_fluxes(h, n: int):
+    ge, gi = np.empty(n), np.empty(n)
+    _check(h, load_library().pic_electrode_fluxes(h, int(n), _ptr(ge, C.c_double), _ptr(gi, C.c_double)))
+    return ge, gi
 
 
 def pic_get_fields(h, n_nodes: int) -> dict:

@@ -20,6 +20,9 @@ hipError_t launch_load(const Params& P, int s, int64_t n, double vth, hipStream_
 hipError_t launch_sort(const Params& P, unsigned* cnt, unsigned* cursor, int blocks, int threads, hipStream_t st);
 hipError_t launch_load_profile(const Params& P, int s, int64_t n, unsigned b, const double* tab, int np, double h_m,
                                hipStream_t st);
+size_t diag_lds_bytes(int nn, int n_bins);
+hipError_t set_diag_lds_limit(size_t bytes);
+hipError_t launch_diag(const Params& P, const DiagDev& D, int blocks, hipStream_t st);
 hipError_t launch_reset_window(const Params& P, hipStream_t st);
 hipError_t set_pass_lds_limit(size_t bytes);
 hipError_t pass_occupancy(int threads, size_t lds, int* blocks_per_cu);
@@ -65,6 +68,10 @@ struct pic_handle {
     unsigned* sort_cnt = nullptr;
     unsigned* sort_cursor = nullptr;
     int8_t* dec_store[2] = {nullptr, nullptr};
+    // diagnostic window (pic_diag_*), allocated by pic_diag_config
+    pic::DiagDev diag{};
+    int diag_capacity_bins = 0;
+    double diag_umax = 0.0;
     int blocks = 1, threads = 256;
     size_t lds = 0;
     int sort_blocks = 1, sort_threads = 256;
@@ -427,7 +434,8 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
             !dev_alloc(h, &P.birth_parent, (size_t)c.max_births_per_step) ||
             !dev_alloc(h, &P.birth_order, (size_t)c.max_births_per_step) || !dev_alloc(h, &tab, std::max<size_t>(ntab, 1)) ||
             !dev_alloc(h, &h->sort_cnt, (size_t)2 * nc + pic::kMaxSortBlocks) ||
-            !dev_alloc(h, &h->sort_cursor, (size_t)2 * nc + pic::kMaxSortBlocks))
+            !dev_alloc(h, &h->sort_cursor, (size_t)2 * nc + pic::kMaxSortBlocks) ||
+            !dev_alloc(h, &P.flux_trace, (size_t)2 * h->spp))
             goto fail_init;
         P.sort_cnt = h->sort_cnt;
         P.sort_cursor = h->sort_cursor;
@@ -539,6 +547,8 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
             !hip_ok(h, hipMemsetAsync(P.rep, 0, pic::kRepSets * pic::kRepStride * sizeof(unsigned long long), h->stream),
                     "zero counter sets") ||
             !hip_ok(h, hipMemsetAsync(P.mom, 0, 5 * nn * sizeof(double), h->stream), "zero moments") ||
+            !hip_ok(h, hipMemsetAsync(P.flux_trace, 0, sizeof(unsigned long long) * 2 * (size_t)h->spp, h->stream),
+                    "zero flux trace") ||
             !hip_ok(h, hipMemsetAsync(h->sort_cnt, 0, (2 * nc + pic::kMaxSortBlocks) * sizeof(unsigned), h->stream),
                     "zero sort counts"))
             goto fail_init;
@@ -820,6 +830,111 @@ int pic_load_profiles(pic_handle* h, int32_t n_points, const double* n_e, const 
         return h->status;
     if (launch_pass_timed(h, pic::kDeposit)) return h->status;
     return check_device(h);
+}
+
+int pic_diag_config(pic_handle* h, int32_t n_bins, double u_max_eV) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (n_bins < 1 || n_bins > 4096) return fail(h, PIC_EINVAL, "n_bins must be in [1, 4096]");
+    if (!(u_max_eV > 0.0) || !std::isfinite(u_max_eV)) return fail(h, PIC_EINVAL, "u_max_eV must be finite and > 0");
+    if (check_device(h)) return h->status;
+    const int nn = h->cfg.n_cells + 1;
+    const size_t lds = pic::diag_lds_bytes(nn, n_bins);
+    if (lds > 160 * 1024) return fail(h, PIC_EINVAL, "n_cells and n_bins need more than 160 KiB of LDS");
+    pic::DiagDev& D = h->diag;
+    if (!D.node) {
+        if (!dev_alloc(h, &D.node, (size_t)8 * nn) || !dev_alloc(h, &D.fx_sample, (size_t)nn) ||
+            !dev_alloc(h, &D.counts, 2))
+            return h->status;
+    }
+    if (n_bins > h->diag_capacity_bins) {
+        if (!dev_alloc(h, &D.hist, (size_t)n_bins)) return h->status;
+        h->diag_capacity_bins = n_bins;
+    }
+    D.n_bins = n_bins;
+    D.bins_per_eV = (float)(n_bins / u_max_eV);
+    D.e0 = kE0;
+    D.n_iz = 0;
+    for (int k = 0; k < h->P.sp_n[0]; ++k)
+        if (h->P.proc[0][k].kind == PIC_E_IONIZATION) D.iz[D.n_iz++] = k;
+    h->diag_umax = u_max_eV;
+    if (!hip_ok(h, pic::set_diag_lds_limit(lds), "hipFuncSetAttribute") ||
+        !hip_ok(h, hipMemsetAsync(D.node, 0, sizeof(double) * 8 * nn, h->stream), "zero diagnostics") ||
+        !hip_ok(h, hipMemsetAsync(D.fx_sample, 0, sizeof(double) * nn, h->stream), "zero diagnostics") ||
+        !hip_ok(h, hipMemsetAsync(D.hist, 0, sizeof(unsigned long long) * n_bins, h->stream), "zero diagnostics") ||
+        !hip_ok(h, hipMemsetAsync(D.counts, 0, sizeof(unsigned long long) * 2, h->stream), "zero diagnostics"))
+        return h->status;
+    return check_device(h);
+}
+
+int pic_diag_sample(pic_handle* h) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (!h->diag.node) return fail(h, PIC_ESTATE, "pic_diag_config was not called");
+    if (complete_pending(h)) return h->status;
+    const int blocks = (int)std::min<int64_t>(512, std::max<int64_t>(1, (h->cfg.capacity[0] + 255) / 256));
+    if (!hip_ok(h, pic::launch_diag(h->P, h->diag, blocks, h->stream), "diag launch")) return h->status;
+    return PIC_OK;
+}
+
+int pic_diag_read(pic_handle* h, pic_diag_out* out, int reset) {
+    if (!h || !out) return h ? fail(h, PIC_EINVAL, "out is NULL") : PIC_EINVAL;
+    if (h->status) return h->status;
+    if (!h->diag.node) return fail(h, PIC_ESTATE, "pic_diag_config was not called");
+    const int nn = h->cfg.n_cells + 1, nb = h->diag.n_bins;
+    if (out->n_nodes != nn) return fail(h, PIC_EINVAL, "out->n_nodes must be n_cells + 1");
+    if (out->eedf_eV_m32 && out->n_bins != nb) return fail(h, PIC_EINVAL, "out->n_bins must be the configured n_bins");
+    if (check_device(h)) return h->status;
+    std::vector<double> node((size_t)8 * nn);
+    std::vector<unsigned long long> hist((size_t)nb), counts(2);
+    if (!hip_ok(h, hipMemcpy(node.data(), h->diag.node, sizeof(double) * node.size(), hipMemcpyDeviceToHost), "copy") ||
+        !hip_ok(h, hipMemcpy(hist.data(), h->diag.hist, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost), "copy") ||
+        !hip_ok(h, hipMemcpy(counts.data(), h->diag.counts, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost),
+                "copy"))
+        return h->status;
+    const double ns = (double)std::max<unsigned long long>(counts[1], 1);
+    const double* n = node.data();
+    for (int i = 0; i < nn; ++i) {
+        const double V = (i == 0 || i == nn - 1) ? 0.5 * h->dx : h->dx;
+        const double f = h->W / (V * ns);
+        if (out->n_e_m3) out->n_e_m3[i] = f * n[i];
+        if (out->mean_energy_e_eV) out->mean_energy_e_eV[i] = n[i] > 0.0 ? n[nn + i] / n[i] : std::nan("");
+        if (out->energy_flux_e_W_m2) out->energy_flux_e_W_m2[i] = f * n[2 * nn + i];
+        if (out->ionisation_rate_m3s) out->ionisation_rate_m3s[i] = f * n[3 * nn + i];
+        if (out->n_fast_m3) out->n_fast_m3[i] = f * n[4 * nn + i];
+        if (out->flux_e_m2s) out->flux_e_m2s[i] = f * n[5 * nn + i];
+        if (out->heating_W_m3) out->heating_W_m3[i] = f * n[6 * nn + i];
+        if (out->E_V_m) out->E_V_m[i] = n[7 * nn + i] / ns;
+    }
+    const double du = h->diag_umax / nb, ne = (double)std::max<unsigned long long>(counts[0], 1);
+    if (out->eedf_eV_m32)
+        for (int k = 0; k < nb; ++k) out->eedf_eV_m32[k] = (double)hist[k] / (ne * du * std::sqrt((k + 0.5) * du));
+    out->n_samples = (int64_t)counts[1];
+    out->n_electrons = (int64_t)counts[0];
+    out->u_max_eV = h->diag_umax;
+    if (reset && (!hip_ok(h, hipMemset(h->diag.node, 0, sizeof(double) * 8 * nn), "zero diagnostics") ||
+                  !hip_ok(h, hipMemset(h->diag.hist, 0, sizeof(unsigned long long) * nb), "zero diagnostics") ||
+                  !hip_ok(h, hipMemset(h->diag.counts, 0, sizeof(unsigned long long) * 2), "zero diagnostics")))
+        return h->status;
+    return PIC_OK;
+}
+
+int pic_electrode_fluxes(pic_handle* h, int32_t n, double* gamma_e, double* gamma_i) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (n != h->spp || !gamma_e || !gamma_i)
+        return fail(h, PIC_EINVAL, "n must be the steps per RF period and the arrays non-NULL");
+    if (check_device(h)) return h->status;
+    std::vector<unsigned long long> t((size_t)2 * n);
+    if (!hip_ok(h, hipMemcpy(t.data(), h->P.flux_trace, sizeof(unsigned long long) * t.size(), hipMemcpyDeviceToHost),
+                "copy flux trace"))
+        return h->status;
+    const double f = h->W / h->cfg.dt_s;
+    for (int k = 0; k < n; ++k) {
+        gamma_e[k] = f * (double)t[2 * k];
+        gamma_i[k] = f * (double)t[2 * k + 1];
+    }
+    return PIC_OK;
 }
 
 int pic_get_fields(pic_handle* h, double* q_nodes, double* phi, float* e_nodes) {

@@ -1026,6 +1026,11 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
                                  P.e0W * ((double)a[0][0] - (double)a[1][0]) / P.dt_d;
                 cs->J_last = J;
                 const int64_t n1 = step + 1;
+                if (P.flux_trace) {   // fluxes at the powered electrode against time
+                    unsigned long long* ft = P.flux_trace + 2 * ((n1 - 1) % P.steps_per_period);
+                    ft[0] = a[0][0];
+                    ft[1] = a[1][0];
+                }
                 cs->J_period_max = fmax(cs->J_period_max, fabs(J));
                 if (n1 % P.steps_per_period == 0) {
                     if (cs->period_valid) {
@@ -1265,6 +1270,98 @@ __global__ void load_profile_kernel(Params P, int s, int64_t n, unsigned b, cons
     P.vy[b][s][k] = (float)(vth * r0 * s0);
     P.vz[b][s][k] = (float)(vth * r1 * c1);
     P.id[b][s][k] = (uint32_t)k;
+}
+
+// ----------------------------------------------------------------------------------
+// Diagnostics of one sample of the completed state (the paper's results section: EEDF,
+// fast electrons, heating, ionisation rate, particle and energy fluxes).  They run between
+// steps, on demand, and leave the particle pass untouched.
+// ----------------------------------------------------------------------------------
+// n_gas sigma [1/m] of process p at frame energy eps [eV], by the particle pass's rule:
+// zero below the threshold, the energy raised to the floor, the last point at or beyond the
+// table end, linear interpolation in between.
+__device__ __forceinline__ float table_ngs(const Params& P, const ProcDev& p, float eps) {
+    if (eps < p.thr) return 0.0f;
+    const float t = fmaxf(eps, p.emin) * p.inv_de;
+    const bool top = t >= (float)(p.n - 1);
+    const int kk = top ? p.n - 2 : (int)t;
+    const float a = P.tab[p.off + kk], b = P.tab[p.off + kk + 1];
+    return top ? b : fmaf(b - a, t - (float)kk, a);
+}
+
+// Each workgroup sums its electrons in LDS (six node grids: weight, U, e0 U v_x, expected
+// ionisation rate n_gas sigma_iz(U) |v|, fast (U > |V0| / 4 with the amplitude in use), v_x;
+// and the energy histogram), then adds them to the window (v_x to this sample's grid).
+__global__ void __launch_bounds__(256) diag_kernel(Params P, DiagDev D) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nn = P.n_cells + 1, tid = threadIdx.x, nt = blockDim.x;
+    float* acc = reinterpret_cast<float*>(smem);
+    unsigned* hist = reinterpret_cast<unsigned*>(acc + 6 * nn);
+    __shared__ unsigned wcount;
+    for (int i = tid; i < 6 * nn; i += nt) acc[i] = 0.0f;
+    for (int i = tid; i < D.n_bins; i += nt) hist[i] = 0u;
+    if (tid == 0) wcount = 0u;
+    __syncthreads();
+    const Ctrl* C = P.ctrl;
+    const unsigned cur = C->cur;
+    const int64_t ns = C->n_slots[0];
+    const float fast = 0.25f * (float)fabs(C->V0);
+    const float* X = bufsel(P.x, cur, 0);
+    const float* VX = bufsel(P.vx, cur, 0);
+    const float* VY = bufsel(P.vy, cur, 0);
+    const float* VZ = bufsel(P.vz, cur, 0);
+    unsigned cnt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * nt + tid; i < ns; i += (int64_t)gridDim.x * nt) {
+        const float x = X[i];
+        if (!(x > 0.0f)) continue;
+        const float vx = VX[i], vy = VY[i], vz = VZ[i];
+        const float g2 = vx * vx + vy * vy + vz * vz;
+        const float U = P.half_m_over_e[0] * g2;
+        const float g = sqrtf(g2);
+        float nu = 0.0f;
+        for (int k = 0; k < D.n_iz; ++k) {
+            const ProcDev& p = P.proc[0][D.iz[k]];
+            nu += table_ngs(P, p, p.efac * g2) * g;
+        }
+        int j;
+        float w;
+        cell_of(x, P.n_cells, j, w);
+        const float vals[6] = {1.0f, U, (float)D.e0 * U * vx, nu, U > fast ? 1.0f : 0.0f, vx};
+        for (int q = 0; q < 6; ++q) {
+            atomicAdd(&acc[q * nn + j], (1.0f - w) * vals[q]);
+            atomicAdd(&acc[q * nn + j + 1], w * vals[q]);
+        }
+        const float b = U * D.bins_per_eV;
+        if (b < (float)D.n_bins) atomicAdd(&hist[(int)b], 1u);
+        ++cnt;
+    }
+    if (cnt) atomicAdd(&wcount, cnt);
+    __syncthreads();
+    for (int i = tid; i < 6 * nn; i += nt) {
+        const float v = acc[i];
+        if (v == 0.0f) continue;
+        const int q = i / nn, node = i - q * nn;
+        if (q == 5) unsafeAtomicAdd(&D.fx_sample[node], (double)v);
+        else unsafeAtomicAdd(&D.node[q * nn + node], (double)v);
+    }
+    for (int i = tid; i < D.n_bins; i += nt)
+        if (hist[i]) atomicAdd(&D.hist[i], (unsigned long long)hist[i]);
+    if (tid == 0 && wcount) atomicAdd(&D.counts[0], (unsigned long long)wcount);
+}
+
+// The sample's node terms: v_x sums into the window, heating -e0 E_i (sum v_x)_i and the
+// field E_i of this time level; clears the sample grid and counts the sample.
+__global__ void diag_nodes_kernel(Params P, DiagDev D) {
+    const int nn = P.n_cells + 1;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += gridDim.x * blockDim.x) {
+        const double fx = D.fx_sample[i];
+        const double E = (double)P.E[i];
+        D.node[5 * nn + i] += fx;
+        D.node[6 * nn + i] += -D.e0 * E * fx;
+        D.node[7 * nn + i] += E;
+        D.fx_sample[i] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) D.counts[1] += 1ull;
 }
 
 // ----------------------------------------------------------------------------------
@@ -1638,6 +1735,22 @@ hipError_t launch_load_profile(const Params& P, int s, int64_t n, unsigned b, co
     const int threads = 256;
     const int64_t blocks = (n + threads - 1) / threads;
     hipLaunchKernelGGL(load_profile_kernel, dim3((unsigned)blocks), dim3(threads), 0, st, P, s, n, b, tab, np, h_m);
+    return hipGetLastError();
+}
+
+size_t diag_lds_bytes(int nn, int n_bins) { return (size_t)6 * nn * sizeof(float) + (size_t)n_bins * sizeof(unsigned); }
+
+hipError_t set_diag_lds_limit(size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&diag_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+hipError_t launch_diag(const Params& P, const DiagDev& D, int blocks, hipStream_t st) {
+    if (blocks < 1 || D.n_bins < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(diag_kernel, dim3(blocks), dim3(256), diag_lds_bytes(P.n_cells + 1, D.n_bins), st, P, D);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(diag_nodes_kernel, dim3((P.n_cells + 256) / 256), dim3(256), 0, st, P, D);
     return hipGetLastError();
 }
 

@@ -148,6 +148,22 @@ struct Params {
     double e0W;               // e0 * W: node charge per unit of deposited weight
     double V0, omega, dt_d;   // V0: the configured amplitude (the one in use is Ctrl::V0)
     double J0_target;         // > 0: current-driven, V0 adapted once per RF period
+    unsigned long long* flux_trace;   // electrons, ions absorbed at z = 0 per step of the RF period [spp][2]
+};
+
+// Diagnostic window (samples of the completed state, off the particle pass).  node holds
+// [8][nn] sums: electron weight, energy U [eV], e0 U v_x, expected ionisation rate, fast
+// electrons, v_x, heating -e0 E (sum v_x), and the field.
+struct DiagDev {
+    double* node;
+    double* fx_sample;           // [nn] this sample's v_x sums, moved into the window by the node pass
+    unsigned long long* hist;    // [n_bins] electron energy histogram over [0, u_max)
+    unsigned long long* counts;  // [2] electrons sampled, samples
+    float bins_per_eV;
+    int n_bins;
+    int n_iz;                    // electron ionisation processes (P.proc[0] indices in iz)
+    int iz[kMaxProcPerSpecies];
+    double e0;
 };
 
 }  // namespace pic

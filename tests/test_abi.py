@@ -40,7 +40,7 @@ def test_library_exports_every_declared_function():
 
 STRUCTS = {
     "pic_xsec": B.pic_xsec, "pic_config": B.pic_config, "pic_moments_out": B.pic_moments_out,
-    "pic_counters": B.pic_counters, "pic_derived": B.pic_derived, "pic_tuning": B.pic_tuning,
+    "pic_counters": B.pic_counters, "pic_derived": B.pic_derived, "pic_tuning": B.pic_tuning, "pic_diag_out": B.pic_diag_out,
 }
 
 

@@ -1,0 +1,89 @@
+"""Diagnostics on the GPU (pic_diag_*, pic_electrode_fluxes) against the oracle's
+diagnostics on the same sampled states, plus exact identities.
+
+Tolerance: the GPU sums each workgroup's share of a sample in FP32 LDS before adding it
+to the FP64 window, and computes U from FP32 velocities: node profiles agree within 1e-4 of
+their largest magnitude; an electron whose FP32 energy falls on the other side of a bin
+edge moves one count between neighbouring bins, so histogram counts agree within 3 per bin
+and in total exactly."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import log, oracle_input
+from oracle import Oracle
+from oracle import diag as OD
+from oracle.pic import derive
+from paper_1608_04601_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+def test_diagnostics_match_oracle():
+    top = 1500.0
+    disc = W.small_argon(seed=7, n_super=30_000).replace(te_init_eV=20.0, processes=W.argon_like(top, top))
+    nn, nb, umax = disc.n_cells + 1, 120, 120.0
+    d_o = derive(disc)
+    win = OD.Window(disc, n_bins=nb, u_max_eV=umax)
+    with B.Discharge(disc) as d:
+        d.step(12)
+        B.pic_diag_config(d.h, nb, umax)
+        for k in range(3):
+            B.pic_diag_sample(d.h)
+            c = d.counters()
+            st = oracle_input(d, c)
+            o = Oracle(disc, load=False)
+            o.V0 = c["V0"]
+            o.set_state(c["step"], st)
+            e = st[0]
+            win.add(e["x"], np.stack([e["vx"], e["vy"], e["vz"]], axis=1), o.E, o.V0, d_o.n_gas)
+            d.step(4)
+        g = B.pic_diag_read(d.h, nn, nb, reset=True)
+        r = win.read(d_o.W)
+        assert g["n_samples"] == 3 and g["n_electrons"] == win.n_electrons
+        for key in ("n_e", "flux_e", "energy_flux_e", "ionisation_rate", "n_fast", "heating", "E"):
+            scale = np.abs(r[key]).max()
+            assert scale > 0, key
+            err = np.abs(g[key] - r[key]).max()
+            log(f"  {key}: max |gpu - oracle| / max|oracle| = {err / scale:.2e}")
+            assert err <= 1e-4 * scale, key
+        dense = r["n_e"] > 1e-3 * r["n_e"].max()
+        np.testing.assert_allclose(g["mean_energy_e"][dense], r["mean_energy_e"][dense], rtol=1e-4)
+        du = umax / nb
+        uc = (np.arange(nb) + 0.5) * du
+        cg = np.rint(g["eedf"] * g["n_electrons"] * du * np.sqrt(uc))
+        assert np.abs(cg - win.hist).max() <= 3 and abs(cg.sum() - win.hist.sum()) <= 0
+        z = B.pic_diag_read(d.h, nn, nb)
+        assert z["n_samples"] == 0 and z["n_electrons"] == 0
+
+
+def test_electrode_fluxes_count_the_absorbed_particles():
+    disc = W.small_argon(seed=9)
+    N = disc.steps_per_period
+    with B.Discharge(disc) as d:
+        d.step(3 * N)
+        a0 = d.counters()["absorbed_total"]
+        d.step(N)
+        a1 = d.counters()["absorbed_total"]
+        ge, gi = B.pic_electrode_fluxes(d.h, N)
+        W_ = B.pic_get_derived(d.h)["W"]
+        got = np.rint(np.array([ge.sum(), gi.sum()]) * disc.dt_s / W_)
+        assert got.tolist() == [a1[0][0] - a0[0][0], a1[1][0] - a0[1][0]]
+        assert ge.min() >= 0.0 and gi.min() >= 0.0 and gi.sum() > 0.0
+
+
+def test_diagnostics_error_paths():
+    disc = W.small_argon(seed=10, n_super=2000)
+    with B.Discharge(disc) as d:
+        with pytest.raises(B.PicError) as e:
+            B.pic_diag_sample(d.h)
+        assert e.value.status == B.PIC_ESTATE
+    with B.Discharge(disc) as d:
+        B.pic_diag_config(d.h, 10, 20.0)
+        with pytest.raises(B.PicError) as e:
+            B.pic_diag_read(d.h, disc.n_cells, 10)
+        assert e.value.status == B.PIC_EINVAL
+    with B.Discharge(disc) as d:
+        with pytest.raises(B.PicError) as e:
+            B.pic_electrode_fluxes(d.h, disc.steps_per_period + 1)
+        assert e.value.status == B.PIC_EINVAL
