@@ -31,6 +31,8 @@ struct mlp_handle {
     uint16_t* dzb[2] = {nullptr, nullptr};
     float* loss = nullptr;
     float* part = nullptr;   // column-sum partials [kColPartsHost x max(width, n_out)]
+    float* ws = nullptr;     // split-K workspace of the weight-gradient products
+    int64_t ws_elems = 0;
     int64_t t = 0;   // Adam steps taken
     int status = PIC_OK;
     std::string err;
@@ -128,6 +130,8 @@ int backward(mlp_handle* h, const float* t, int64_t batch) {
         gw.K = (int)batch;
         gw.Cf = h->g + h->w_off[l];
         gw.ldc = i;
+        gw.ws = h->ws;
+        gw.ws_elems = h->ws_elems;
         if (!mok(h, mlp::launch_gemm(gw, h->stream), "gemm launch") ||
             !mok(h, mlp::launch_colsum(h->dzf[cur], batch, o, h->part, h->g + h->b_off[l], h->stream), "colsum launch"))
             return h->status;
@@ -193,6 +197,11 @@ int mlp_init(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, int32_t 
     bool ok = alloc(h, &h->p, P) && alloc(h, &h->pb, P) && alloc(h, &h->g, P) && alloc(h, &h->m, P) &&
               alloc(h, &h->v, P) && alloc(h, &h->y, (int64_t)max_batch * n_out) && alloc(h, &h->loss, 1) &&
               alloc(h, &h->part, (int64_t)mlp::kColPartsHost * dmax);
+    // up to 32 K-chunks of the largest weight gradient
+    int64_t wmax = 0;
+    for (int l = 0; l <= depth; ++l) wmax = std::max<int64_t>(wmax, (int64_t)h->out_dim[l] * h->in_dim[l]);
+    h->ws_elems = 32 * wmax;
+    ok = ok && alloc(h, &h->ws, h->ws_elems);
     for (int q = 0; ok && q < 2; ++q)
         ok = alloc(h, &h->dzf[q], (int64_t)max_batch * dmax) && alloc(h, &h->dzb[q], (int64_t)max_batch * dmax);
     h->act.assign(depth + 1, nullptr);

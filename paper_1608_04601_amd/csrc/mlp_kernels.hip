@@ -7,6 +7,7 @@
 // fused epilogue: + bias[n], ReLU, a ReLU-derivative mask, FP32 and/or BF16 output.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "mlp_types.hpp"
@@ -34,7 +35,7 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 // D[4 (l / 16) + q][l % 16] (q = 0..3).
 constexpr int kBM = 64, kBN = 64, kBK = 32, kLDK = kBK + 8;
 
-__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g, int k_split, float* __restrict__ part) {
     __shared__ __align__(16) uint16_t As[kBM * kLDK];
     __shared__ __align__(16) uint16_t Bs[kBN * kLDK];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -43,7 +44,9 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
     f32x4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+    const int64_t kb = (int64_t)blockIdx.z * k_split;
+    const int64_t ke = kb + k_split < g.K ? kb + k_split : g.K;
+    for (int64_t k0 = kb; k0 < ke; k0 += kBK) {
         // Stage the 64 x 32 tiles: 16-byte loads of 8 operands where a tile row (or column)
         // is contiguous in memory and 8-aligned (one load per thread per tile), else one
         // element at a time.  Out-of-range operands are zero.
@@ -51,40 +54,40 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
             const int r = tid >> 2, c = (tid & 3) * 8;
             const int64_t m = m0 + r, k = k0 + c;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (m < g.M && k < g.K) v = *reinterpret_cast<const uint4*>(g.A + m * g.sam + k);
+            if (m < g.M && k < ke) v = *reinterpret_cast<const uint4*>(g.A + m * g.sam + k);
             *reinterpret_cast<uint4*>(&As[r * kLDK + c]) = v;
         } else if (g.vec_a == 2) {   // contiguous along m
             const int c = tid >> 3, r = (tid & 7) * 8;
             const int64_t m = m0 + r, k = k0 + c;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (m < g.M && k < g.K) v = *reinterpret_cast<const uint4*>(g.A + m + k * g.sak);
+            if (m < g.M && k < ke) v = *reinterpret_cast<const uint4*>(g.A + m + k * g.sak);
             const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
             for (int j = 0; j < 8; ++j) As[(r + j) * kLDK + c] = h[j];
         } else {
             for (int e = tid; e < kBM * kBK; e += 256) {
                 const int r = e / kBK, c = e % kBK;
                 const int64_t m = m0 + r, k = k0 + c;
-                As[r * kLDK + c] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : (uint16_t)0;
+                As[r * kLDK + c] = (m < g.M && k < ke) ? g.A[m * g.sam + k * g.sak] : (uint16_t)0;
             }
         }
         if (g.vec_b == 1) {   // contiguous along k
             const int r = tid >> 2, c = (tid & 3) * 8;
             const int64_t n = n0 + r, k = k0 + c;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (n < g.N && k < g.K) v = *reinterpret_cast<const uint4*>(g.B + k + n * g.sbn);
+            if (n < g.N && k < ke) v = *reinterpret_cast<const uint4*>(g.B + k + n * g.sbn);
             *reinterpret_cast<uint4*>(&Bs[r * kLDK + c]) = v;
         } else if (g.vec_b == 2) {   // contiguous along n
             const int c = tid >> 3, r = (tid & 7) * 8;
             const int64_t n = n0 + r, k = k0 + c;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (n < g.N && k < g.K) v = *reinterpret_cast<const uint4*>(g.B + k * g.sbk + n);
+            if (n < g.N && k < ke) v = *reinterpret_cast<const uint4*>(g.B + k * g.sbk + n);
             const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
             for (int j = 0; j < 8; ++j) Bs[(r + j) * kLDK + c] = h[j];
         } else {
             for (int e = tid; e < kBN * kBK; e += 256) {
                 const int r = e / kBK, c = e % kBK;
                 const int64_t n = n0 + r, k = k0 + c;
-                Bs[r * kLDK + c] = (n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : (uint16_t)0;
+                Bs[r * kLDK + c] = (n < g.N && k < ke) ? g.B[k * g.sbk + n * g.sbn] : (uint16_t)0;
             }
         }
         __syncthreads();
@@ -103,6 +106,10 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
                 const int64_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
                 const int64_t n = n0 + wn + 16 * j + (lane & 15);
                 if (m >= g.M || n >= g.N) continue;
+                if (part) {
+                    part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][q];
+                    continue;
+                }
                 float v = acc[i][j][q];
                 if (g.bias) v += g.bias[n];
                 if (g.relu) v = fmaxf(v, 0.0f);
@@ -110,6 +117,131 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
                 if (g.Cf) g.Cf[m * g.ldc + n] = v;
                 if (g.Cb) g.Cb[m * g.ldc + n] = to_bf16(v);
             }
+}
+
+// The epilogue of one output element: bias, ReLU, mask, FP32 and/or BF16 store.
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, int64_t m, int64_t n, float v) {
+    if (g.bias) v += g.bias[n];
+    if (g.relu) v = fmaxf(v, 0.0f);
+    if (g.mask && !(from_bf16(g.mask[m * g.ldc + n]) > 0.0f)) v = 0.0f;
+    if (g.Cf) g.Cf[m * g.ldc + n] = v;
+    if (g.Cb) g.Cb[m * g.ldc + n] = to_bf16(v);
+}
+
+// Large tiles for operands that both stage with 16-byte loads (vec_a, vec_b != 0): a
+// workgroup computes 128 x 128 of C, each wave 64 x 64 as 4 x 4 MFMA blocks, K in steps of
+// 32 through two LDS buffers: the next step's tiles are loaded into registers while the
+// current step's 16 MFMAs per wave run, then stored to the other buffer, one barrier per
+// step.  blockIdx.z splits K into chunks of k_split (a multiple of 32): with more than one
+// chunk, raw sums go to part[z][M][N] and gemm_reduce_kernel finishes them.
+constexpr int kTM = 128, kTN = 128, kTLD = kBK + 8;
+
+__device__ __forceinline__ void stage_load(const uint16_t* base, int vec, int64_t s_outer, int64_t s_inner,
+                                           int64_t o0, int64_t k0, int64_t O, int64_t ke, int c, uint4& v,
+                                           int& ro, int& rk) {
+    // chunk c of the 128 x 32 tile: vec 1 -> 8 consecutive k of row ro; vec 2 -> 8
+    // consecutive rows from ro at column rk
+    if (vec == 1) {
+        ro = c >> 2;
+        rk = (c & 3) * 8;
+    } else {
+        rk = c >> 4;
+        ro = (c & 15) * 8;
+    }
+    const int64_t o = o0 + ro, k = k0 + rk;
+    v = make_uint4(0u, 0u, 0u, 0u);
+    if (o < O && k < ke)
+        v = *reinterpret_cast<const uint4*>(base + (vec == 1 ? o * s_outer + k : o + k * s_inner));
+}
+
+__device__ __forceinline__ void stage_store(uint16_t* lds, int vec, const uint4& v, int ro, int rk) {
+    if (vec == 1) {
+        *reinterpret_cast<uint4*>(&lds[ro * kTLD + rk]) = v;
+    } else {
+        const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) lds[(ro + j) * kTLD + rk] = (uint16_t)(wd[j >> 1] >> (16 * (j & 1)));
+    }
+}
+
+__global__ void __launch_bounds__(256) gemm_bf16_big_kernel(GemmArgs g, int k_split, float* __restrict__ part) {
+    __shared__ __align__(16) uint16_t As[2][kTM * kTLD];
+    __shared__ __align__(16) uint16_t Bs[2][kTN * kTLD];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.y * kTM, n0 = (int64_t)blockIdx.x * kTN;
+    const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+    const int64_t kb = (int64_t)blockIdx.z * k_split;
+    const int64_t ke = kb + k_split < g.K ? kb + k_split : g.K;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // A is (outer m, inner k): m stride sam, k stride sak; B^T is (outer n, inner k)
+    uint4 ra[2], rb[2];
+    int rao[2], rak[2], rbo[2], rbk[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        stage_load(g.A, g.vec_a, g.sam, g.sak, m0, kb, g.M, ke, tid + 256 * u, ra[u], rao[u], rak[u]);
+        stage_load(g.B, g.vec_b, g.sbn, g.sbk, n0, kb, g.N, ke, tid + 256 * u, rb[u], rbo[u], rbk[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        stage_store(As[0], g.vec_a, ra[u], rao[u], rak[u]);
+        stage_store(Bs[0], g.vec_b, rb[u], rbo[u], rbk[u]);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = kb; k0 < ke; k0 += kBK) {
+        const bool more = k0 + kBK < ke;
+        if (more)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                stage_load(g.A, g.vec_a, g.sam, g.sak, m0, k0 + kBK, g.M, ke, tid + 256 * u, ra[u], rao[u], rak[u]);
+                stage_load(g.B, g.vec_b, g.sbn, g.sbk, n0, k0 + kBK, g.N, ke, tid + 256 * u, rb[u], rbo[u], rbk[u]);
+            }
+        bf16x8 a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][(wm + 16 * i + (lane & 15)) * kTLD + 8 * (lane >> 4)]);
+            b[i] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn + 16 * i + (lane & 15)) * kTLD + 8 * (lane >> 4)]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (more)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                stage_store(As[buf ^ 1], g.vec_a, ra[u], rao[u], rak[u]);
+                stage_store(Bs[buf ^ 1], g.vec_b, rb[u], rbo[u], rbk[u]);
+            }
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+                const int64_t n = n0 + wn + 16 * j + (lane & 15);
+                if (m < g.M && n < g.N) {
+                    if (part) part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][q];
+                    else gemm_store(g, m, n, acc[i][j][q]);
+                }
+            }
+}
+
+// Split-K finish: each element sums its chunks in order, then the epilogue.
+__global__ void gemm_reduce_kernel(GemmArgs g, int splits, const float* __restrict__ part) {
+    const int64_t total = (int64_t)g.M * g.N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.0f;
+        for (int z = 0; z < splits; ++z) v += part[(int64_t)z * total + e];
+        gemm_store(g, e / g.N, e % g.N, v);
+    }
 }
 
 __global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t n) {
@@ -209,8 +341,27 @@ hipError_t launch_gemm(const GemmArgs& g0, hipStream_t st) {
     g.vec_b = 0;
     if (aligned(g.B) && g.sbk == 1 && g.K % 8 == 0 && g.sbn % 8 == 0) g.vec_b = 1;
     else if (aligned(g.B) && g.sbn == 1 && g.N % 8 == 0 && g.sbk % 8 == 0) g.vec_b = 2;
-    const dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM));
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, g);
+    const bool big = g.vec_a && g.vec_b;
+    const int64_t tm = (g.M + (big ? kTM : kBM) - 1) / (big ? kTM : kBM);
+    const int64_t tn = (g.N + (big ? kTN : kBN) - 1) / (big ? kTN : kBN);
+    // split K when the tiles alone cannot fill the device: chunks of at least 512, at most
+    // 256 workgroups in all, within the workspace
+    int splits = 1;
+    if (g.ws && tm * tn < 128 && g.K >= 1024) {
+        int64_t s = std::min<int64_t>(g.K / 512, 256 / (tm * tn));
+        s = std::min<int64_t>(s, g.ws_elems / ((int64_t)g.M * g.N));
+        splits = (int)std::max<int64_t>(1, s);
+    }
+    int64_t k_split = (g.K + splits - 1) / splits;
+    k_split = (k_split + kBK - 1) / kBK * kBK;
+    splits = (int)((g.K + k_split - 1) / k_split);
+    const dim3 grid((unsigned)tn, (unsigned)tm, (unsigned)splits);
+    float* part = splits > 1 ? g.ws : nullptr;
+    if (big) hipLaunchKernelGGL(gemm_bf16_big_kernel, grid, dim3(256), 0, st, g, (int)k_split, part);
+    else hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, g, (int)k_split, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || splits == 1) return e;
+    hipLaunchKernelGGL(gemm_reduce_kernel, dim3(grid_for((int64_t)g.M * g.N, 256)), dim3(256), 0, st, g, splits, g.ws);
     return hipGetLastError();
 }
 

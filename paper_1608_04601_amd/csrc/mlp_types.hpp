@@ -22,6 +22,8 @@ struct GemmArgs {
     uint16_t* Cb;
     int64_t ldc;
     int vec_a, vec_b;   // staging mode, chosen by launch_gemm
+    float* ws;          // split-K workspace (may be null: no split)
+    int64_t ws_elems;
 };
 
 constexpr int kColPartsHost = 64;   // partial sums per column of launch_colsum

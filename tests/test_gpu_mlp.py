@@ -7,7 +7,8 @@ rounded operands per layer over up to four layers, the result carries a relative
 a few times 1e-2 at most in the max norm; the tests allow 3e-2 of each tensor's largest
 magnitude (forward), a relative L2 error of 3e-2 for the gradient, and require the
 gradient's direction (cosine) to agree to 0.999.  The shapes include ragged tiles
-(dimensions that are not multiples of the 64 x 64 x 32 GEMM tile)."""
+(dimensions that are not multiples of the GEMM tiles) and a batch whose weight gradients
+split K across workgroups."""
 import numpy as np
 import pytest
 import torch
@@ -18,7 +19,9 @@ from paper_1608_04601_amd import binding as B
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = {"surrogate_4x256x3x640": (4, 256, 3, 640, 512), "ragged_5x70x2x33": (5, 70, 2, 33, 77)}
+SHAPES = {"surrogate_4x256x3x640": (4, 256, 3, 640, 512), "ragged_5x70x2x33": (5, 70, 2, 33, 77),
+          # batch 2048: the weight gradients split K over several workgroups
+          "surrogate_batch2048": (4, 256, 3, 640, 2048)}
 
 
 def _data(n_in, n_out, batch, seed):
