@@ -19,6 +19,7 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_PARTICLE_STEP = 36   # read x, vx, vy, vz, id (20 B) + write x, vx, vy, vz (16 B), FP32/u32
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # dense BF16 matrix-core peak
 
 
 def workloads_by_name():
@@ -248,20 +249,29 @@ def run_mlp(args, B, torch):
         flop = flop_fwd * batch * (1 if name == "forward" else 3)   # backward: two GEMMs per layer
         res[name] = {"batch": batch, "ms": ms, "TFLOP_s": flop / (ms * 1e-3) / 1e12}
         net.close()
-    peak = 2500.0
+    # algorithmic bytes of the forward pass per sample: the FP32 input read and its BF16 copy
+    # written and read, each hidden activation written and read in BF16, the FP32 output
+    # written (weights are negligible at this batch)
+    bytes_fwd = 4 * 4 + 2 * 4 + 2 * 4 + sum(2 * 2 * d for d in dims[1:4]) + 4 * dims[4]
+    fwd = res["forward"]
+    gbs = bytes_fwd * fwd["batch"] / (fwd["ms"] * 1e-3) / 1e9
+    ai = flop_fwd / bytes_fwd
     out = {
         "metric": "surrogate network throughput (BF16 MFMA, FP32 accumulate)",
-        "value": res["forward"]["TFLOP_s"],
+        "value": fwd["TFLOP_s"],
         "unit": "TFLOP/s (forward)",
         "n_gpus": 1,
         "higher_is_better": True,
         "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": "mlp_4x256x3x640", "flop_per_sample_forward": flop_fwd},
-        "roofline": {"bound": "mfma", "achieved": res["forward"]["TFLOP_s"], "peak": peak, "unit": "TFLOP/s",
-                     "frac": res["forward"]["TFLOP_s"] / peak},
+        "config": {"workload": "mlp_4x256x3x640", "flop_per_sample_forward": flop_fwd,
+                   "bytes_per_sample_forward": bytes_fwd, "flop_per_byte": ai},
+        # below the ridge (2500 TFLOP/s / 8 TB/s = 312 FLOP/B) the forward pass is bound by HBM
+        "roofline": {"bound": "hbm" if ai < MFMA_BF16_PEAK_TFLOPS / HBM_PEAK_GBS * 1e3 else "mfma",
+                     "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "mfma_frac": fwd["TFLOP_s"] / MFMA_BF16_PEAK_TFLOPS},
         "train_step": res["train_step"],
-        "forward": res["forward"],
+        "forward": fwd,
     }
     print(json.dumps(out), flush=True)
 
