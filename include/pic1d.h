@@ -323,6 +323,12 @@ int pic_batch_step(pic_batch* b, int64_t n_steps);
  * stream; it holds kernel launches only. */
 int pic_batch_set_graph(pic_batch* b, int64_t steps_per_graph);
 
+/* Completes every discharge's pending step, then splits the workgroups of batched launches
+ * anew in proportion to the particles alive now (the split made at pic_batch_init follows
+ * the initial counts, which a warm start or an ionising transient can change several-fold).
+ * Drops any captured graph.  Results do not depend on the split. */
+int pic_batch_rebalance(pic_batch* b);
+
 /* Number of graph replays since the last pic_batch_set_graph (for tests). */
 int pic_batch_graph_launches(const pic_batch* b, int64_t* n);
 

@@ -21,7 +21,7 @@ EXPORTED = ("pic_init", "pic_step", "pic_sync", "pic_moments", "pic_free", "pic_
             "pic_get_fields", "pic_set_record_decisions", "pic_get_decisions", "pic_timing",
             "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
             "pic_batch_free", "pic_batch_last_error", "pic_batch_timing", "pic_batch_set_graph",
-            "pic_batch_graph_launches", "pic_batch_autotune",
+            "pic_batch_graph_launches", "pic_batch_autotune", "pic_batch_rebalance",
             "pic_load_profiles", "pic_diag_config", "pic_diag_sample", "pic_diag_read", "pic_electrode_fluxes",
             "mlp_init", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_gradient",
             "mlp_train_step", "mlp_free", "mlp_last_error")
@@ -142,6 +142,7 @@ def load_library(path: str = None):
         "pic_batch_set_graph": (C.c_int, [C.c_void_p, C.c_int64]),
         "pic_batch_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
         "pic_batch_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
+        "pic_batch_rebalance": (C.c_int, [C.c_void_p]),
         "pic_load_profiles": (C.c_int, [H, C.c_int32, dp, dp, dp, dp]),
         "pic_diag_config": (C.c_int, [H, C.c_int32, C.c_double]),
         "pic_diag_sample": (C.c_int, [H]),
@@ -398,6 +399,10 @@ class Batch:
     def set_graph(self, steps_per_graph):
         """Replay runs of steps_per_graph steps from a captured HIP graph (0: launch each step)."""
         _check_batch(self.b, load_library().pic_batch_set_graph(self.b, int(steps_per_graph)))
+
+    def rebalance(self):
+        """Split the workgroups anew by the particles alive now."""
+        _check_batch(self.b, load_library().pic_batch_rebalance(self.b))
 
     def graph_launches(self):
         n = C.c_int64()

@@ -1354,6 +1354,24 @@ int pic_batch_set_graph(pic_batch* b, int64_t steps_per_graph) {
     return PIC_OK;
 }
 
+int pic_batch_rebalance(pic_batch* b) {
+    if (!b) return PIC_EINVAL;
+    if (pic_batch_sync(b)) return b->status;
+    std::vector<double> w;
+    for (pic_handle* h : b->hs) {
+        pic::Ctrl c;
+        if (read_ctrl(h, &c)) return batch_status(b);
+        w.push_back((double)std::max<int64_t>(1, c.n_alive[0] + c.n_alive[1]));
+    }
+    if (b->gexec) {   // the launch shape changes
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    const hipError_t e = batch_layout(b, b->threads, b->rounds, w);
+    if (e != hipSuccess) return bfail(b, PIC_EHIP, std::string("batch layout: ") + hipGetErrorString(e));
+    return PIC_OK;
+}
+
 int pic_batch_graph_launches(const pic_batch* b, int64_t* n) {
     if (!b || !n) return PIC_EINVAL;
     *n = b->graph_launches;

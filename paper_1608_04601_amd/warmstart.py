@@ -129,6 +129,7 @@ def run(discs, max_periods, warm=None, stream=None, log=None):
             for k, w in enumerate(warm):
                 if w is not None:
                     B.pic_load_profiles(bt[k].h, w["n_e"], w["n_i"], w["mean_energy_e"], w["flux_i"])
+        bt.rebalance()   # a warm load changes the particle counts
         bt.set_graph(spp)
         det = [SteadyState() for _ in discs]
         prev = [(bt[k].counters()["births_total"], int(bt[k].counters()["absorbed_total"][1].sum()))
@@ -137,6 +138,8 @@ def run(discs, max_periods, warm=None, stream=None, log=None):
             bt[k].moments(reset=True)
         t0 = time.time()
         for c in range(max_periods):
+            if c % 50 == 49:
+                bt.rebalance()   # the counts drift while the discharges relax
             bt.step(spp)
             bt.sync()
             for k, d in enumerate(discs):

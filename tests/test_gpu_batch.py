@@ -111,6 +111,30 @@ def test_graph_replays_equal_eager_steps():
         log(f"graph replays checked: {replays}")
 
 
+def test_rebalance_keeps_results():
+    """Re-splitting the workgroups by the current counts (after a warm load of one member,
+    which changes its count several-fold) changes no result."""
+    discs = _common_sort_members()
+    z = np.linspace(0.0, discs[0].gap_m, 33)
+    prof = dict(n_e=3e15 * np.sin(np.pi * z / z[-1]) ** 2 + 1e13, n_i=3e15 * np.sin(np.pi * z / z[-1]) + 1e13,
+                mean_energy_e=np.full(33, 3.0), flux_i=np.zeros(33))
+    with B.Batch(discs) as bt:
+        B.pic_load_profiles(bt[0].h, prof["n_e"], prof["n_i"], prof["mean_energy_e"], prof["flux_i"])
+        g0 = bt.blocks(0)
+        bt.rebalance()
+        assert bt.blocks(0) > g0
+        bt.step(12)
+        bt.rebalance()
+        bt.step(9)
+        got = [_state(bt[k]) for k in range(len(bt))]
+    for k, d in enumerate(discs):
+        with B.Discharge(d) as solo:
+            if k == 0:
+                B.pic_load_profiles(solo.h, prof["n_e"], prof["n_i"], prof["mean_energy_e"], prof["flux_i"])
+            solo.step(21)
+            _same(got[k], _state(solo), k)
+
+
 def test_autotune_choice_is_valid_and_keeps_results():
     """The tuner's trials advance the batch under other launch shapes and reordering
     schedules; the state must still equal, per id, each discharge advanced alone by the
