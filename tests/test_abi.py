@@ -134,3 +134,26 @@ def test_mlp_invalid_arguments_rejected_on_host():
     assert L.mlp_init(4, 8, 1, 4, 16, 0, None, None) == B.PIC_EINVAL
     assert L.mlp_train_step(None, None, None, 1, 1e-3, None) == B.PIC_EINVAL
     L.mlp_free(None)
+
+
+def test_new_entry_points_reject_null_on_host():
+    """Batches, warm start, diagnostics and current drive: NULL handles are rejected before
+    any device work, and a negative current target is an invalid configuration."""
+    L = B.load_library()
+    for f, args in ((L.pic_batch_set_graph, (None, 10)), (L.pic_batch_autotune, (None, 10, None)),
+                    (L.pic_batch_rebalance, (None,)), (L.pic_batch_timing, (None, 1, None, None)),
+                    (L.pic_diag_config, (None, 10, 20.0)), (L.pic_diag_sample, (None,)),
+                    (L.pic_diag_read, (None, None, 0)), (L.pic_electrode_fluxes, (None, 10, None, None)),
+                    (L.pic_load_profiles, (None, 3, None, None, None, None))):
+        assert f(*args) == B.PIC_EINVAL, f.__name__
+    n = C.c_int64()
+    assert L.pic_batch_graph_launches(None, C.byref(n)) == B.PIC_EINVAL
+    assert L.mlp_num_params(None, C.byref(n)) == B.PIC_EINVAL
+
+
+@pytest.mark.parametrize("j0", [-1.0, float("nan"), float("inf")])
+def test_invalid_current_target_rejected_on_host(j0):
+    cfg = B.Config(W.small_argon(n_super=100).replace(j0_target_A_m2=j0))
+    h = C.c_void_p()
+    assert B.load_library().pic_init(C.byref(cfg.c), None, C.byref(h)) == B.PIC_EINVAL and not h
+    assert b"j0_target" in B.load_library().pic_last_error(None)
