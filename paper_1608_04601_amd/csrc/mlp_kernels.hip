@@ -165,8 +165,10 @@ __device__ __forceinline__ void stage_store(uint16_t* lds, int vec, const uint4&
 }
 
 __global__ void __launch_bounds__(256) gemm_bf16_big_kernel(GemmArgs g, int k_split, float* __restrict__ part) {
-    __shared__ __align__(16) uint16_t As[2][kTM * kTLD];
-    __shared__ __align__(16) uint16_t Bs[2][kTN * kTLD];
+    // staging buffers, reused for the output tile after the K loop
+    __shared__ __align__(16) uint16_t lds[2 * 2 * kTM * kTLD];
+    uint16_t(*As)[kTM * kTLD] = reinterpret_cast<uint16_t(*)[kTM * kTLD]>(lds);
+    uint16_t(*Bs)[kTN * kTLD] = reinterpret_cast<uint16_t(*)[kTN * kTLD]>(lds + 2 * kTM * kTLD);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t m0 = (int64_t)blockIdx.y * kTM, n0 = (int64_t)blockIdx.x * kTN;
     const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
@@ -219,19 +221,77 @@ __global__ void __launch_bounds__(256) gemm_bf16_big_kernel(GemmArgs g, int k_sp
         __syncthreads();
         buf ^= 1;
     }
+    if (part) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
-                const int64_t n = n0 + wn + 16 * j + (lane & 15);
-                if (m < g.M && n < g.N) {
-                    if (part) part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][q];
-                    else gemm_store(g, m, n, acc[i][j][q]);
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+                    const int64_t n = n0 + wn + 16 * j + (lane & 15);
+                    if (m < g.M && n < g.N) part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][q];
                 }
+        return;
+    }
+    // Output through LDS: each wave writes 32 of its 64 rows at a time (8 KiB per wave), then
+    // every lane takes runs of 8 consecutive columns of a row, applies the epilogue and
+    // stores them with 16-byte vector stores where the run is whole and 8-aligned.
+    float* ot = reinterpret_cast<float*>(lds) + w * 32 * 64;
+    const bool vec_out = (g.ldc % 8) == 0 && (!g.Cf || (reinterpret_cast<uintptr_t>(g.Cf) & 15u) == 0) &&
+                         (!g.Cb || (reinterpret_cast<uintptr_t>(g.Cb) & 15u) == 0) &&
+                         (!g.mask || (reinterpret_cast<uintptr_t>(g.mask) & 15u) == 0);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    ot[(16 * i + 4 * (lane >> 4) + q) * 64 + 16 * j + (lane & 15)] = acc[2 * half + i][j][q];
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int idx = t * 64 + lane, r = idx >> 3, c = (idx & 7) * 8;
+            const int64_t m = m0 + wm + 32 * half + r, n = n0 + wn + c;
+            if (m >= g.M) continue;
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = ot[r * 64 + c + e];
+            if (vec_out && n + 8 <= g.N) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if (g.bias) v[e] += g.bias[n + e];
+                    if (g.relu) v[e] = fmaxf(v[e], 0.0f);
+                }
+                if (g.mask) {
+                    const uint4 mk = *reinterpret_cast<const uint4*>(g.mask + m * g.ldc + n);
+                    const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        if (!(from_bf16((uint16_t)(mw[e >> 1] >> (16 * (e & 1)))) > 0.0f)) v[e] = 0.0f;
+                }
+                if (g.Cf) {
+                    float4* dst = reinterpret_cast<float4*>(g.Cf + m * g.ldc + n);
+                    dst[0] = make_float4(v[0], v[1], v[2], v[3]);
+                    dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+                }
+                if (g.Cb) {
+                    uint32_t pk[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        pk[e] = (uint32_t)to_bf16(v[2 * e]) | ((uint32_t)to_bf16(v[2 * e + 1]) << 16);
+                    *reinterpret_cast<uint4*>(g.Cb + m * g.ldc + n) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (n + e < g.N) gemm_store(g, m, n + e, v[e]);
             }
+        }
+        __syncthreads();
+    }
 }
 
 // Split-K finish: each element sums its chunks in order, then the epilogue.
