@@ -87,3 +87,18 @@ def test_diagnostics_error_paths():
         with pytest.raises(B.PicError) as e:
             B.pic_electrode_fluxes(d.h, disc.steps_per_period + 1)
         assert e.value.status == B.PIC_EINVAL
+
+
+def test_phase_resolved_driver_samples_once_per_period():
+    from paper_1608_04601_amd import diagnostics as DG
+    disc = W.small_argon(seed=11, n_super=5000)
+    N = disc.steps_per_period
+    with B.Discharge(disc) as d:
+        r = DG.phase_resolved(d, disc, periods=3, phase=0.25, n_bins=50, u_max_eV=50.0)
+        assert r["n_samples"] == 3 and d.counters()["step"] == 3 * N
+        # at t f = 0.25 the powered electrode is at +V0 and z = d the momentary cathode: the
+        # potential falls from the plasma (at or above V0) to 0 there, so E(d) > 0
+        assert r["E"][-1] > 0.0
+        t = DG.time_averaged(d, disc, periods=1, every=N // 8, n_bins=50, u_max_eV=50.0)
+        assert t["n_samples"] == 8
+        assert np.all(np.isfinite(t["eedf"])) and t["eedf"].sum() > 0
