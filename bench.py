@@ -190,10 +190,17 @@ def run_warmstart(args, B, torch):
     t0 = time.time()
     net, norm, loss = WS.train(data["params"][keep], data["profiles"][keep], steps=4000)
     train_s = time.time() - t0
-    params = W.surrogate_params(args.ws_n, 2)
     t1 = time.time()
-    rows = WS.evaluate(net, norm, params, 2, args.ws_periods,
-                       log=lambda m: print(m, file=sys.stderr, flush=True))
+    if args.ws_target == "production":
+        # the production helium discharge at full fidelity (512 cells, 1e6 particles per
+        # species, T_rf/2000), storage for 4x its initial count
+        disc = W.production_helium().replace(capacity=(4_000_000, 4_000_000))
+        rows = [WS.evaluate_discharge(net, norm, disc, 1, args.ws_periods,
+                                      log=lambda m: print(m, file=sys.stderr, flush=True))]
+    else:
+        params = W.surrogate_params(args.ws_n, 2)
+        rows = WS.evaluate(net, norm, params, 2, args.ws_periods,
+                           log=lambda m: print(m, file=sys.stderr, flush=True))
     eval_s = time.time() - t1
     sm = WS.summarize(rows, args.ws_periods)
     if args.ws_out:
@@ -210,9 +217,12 @@ def run_warmstart(args, B, torch):
         "vs_baseline": None,
         "dtype": "f32 particles, bf16 network",
         "data": "synthetic",
-        "config": {"workload": f"surrogate_heldout_{args.ws_n}", "training_steady_states": int(keep.sum()),
-                   "period_limit": args.ws_periods, "cells": 128, "steps_per_rf_period": 1000,
-                   "particles_per_species_initial": 20000},
+        "config": ({"workload": f"surrogate_heldout_{args.ws_n}", "training_steady_states": int(keep.sum()),
+                    "period_limit": args.ws_periods, "cells": 128, "steps_per_rf_period": 1000,
+                    "particles_per_species_initial": 20000} if args.ws_target == "heldout" else
+                   {"workload": "helium_2.5cm_512c_40Pa_200V", "training_steady_states": int(keep.sum()),
+                    "period_limit": args.ws_periods, "cells": 512, "steps_per_rf_period": 2000,
+                    "particles_per_species_initial": 1000000}),
         "summary": sm,
         "train_s": train_s,
         "train_loss": loss,
@@ -285,6 +295,8 @@ def main():
     ap.add_argument("--ws-n", type=int, default=16, help="warmstart: held-out discharges")
     ap.add_argument("--ws-periods", type=int, default=1500, help="warmstart: RF period limit")
     ap.add_argument("--ws-out", default=None, help="warmstart: write every discharge's result (JSON)")
+    ap.add_argument("--ws-target", default="heldout", choices=("heldout", "production"),
+                    help="warmstart: held-out draws of the training family, or the production discharge")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps of the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-blocks", type=int, default=0)

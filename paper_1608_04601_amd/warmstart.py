@@ -282,6 +282,19 @@ def evaluate(net, norm, params, seed, max_periods, log=None, index=None):
     return rows
 
 
+def evaluate_discharge(net, norm, disc, gas_id, max_periods, log=None):
+    """One discharge of any fidelity, cold and warm in one batch.  The network sees its
+    (p, V0, d, gas id); the prediction is resampled onto the loader's points."""
+    params = np.array([[disc.pressure_Pa, disc.rf_voltage_V, disc.gap_m, float(gas_id)]])
+    pred = predict(net, norm, params)[0]
+    res = run([disc, disc], max_periods, warm=[None, warm_profiles(pred)], log=log)
+    cold, hot = res
+    return dict(params=[float(v) for v in params[0]], cold_steady_at=cold["steady_at"], warm_steady_at=hot["steady_at"],
+                extinct=bool(cold["extinct"] or hot["extinct"]), warm_vs_cold=profile_change(hot["final"], cold["final"]).tolist(),
+                prediction_vs_cold=profile_change(pred, cold["final"]).tolist(), alive_cold=cold["alive"],
+                alive_warm=hot["alive"])
+
+
 def summarize(rows, max_periods):
     ok = [r for r in rows if not r["extinct"]]
     both = [r for r in ok if r["cold_steady_at"] is not None and r["warm_steady_at"] is not None]
