@@ -197,12 +197,25 @@ def run_warmstart(args, B, torch):
         disc = W.production_helium().replace(capacity=(4_000_000, 4_000_000))
         rows = [WS.evaluate_discharge(net, norm, disc, 1, args.ws_periods,
                                       log=lambda m: print(m, file=sys.stderr, flush=True))]
+    elif args.ws_target == "large":
+        # the large argon discharge (4096 cells, T_rf/4000) weighted for ~2.5e7 particles
+        # per species in its periodic state
+        disc = W.large_argon_periodic()
+        rows = [WS.evaluate_discharge(net, norm, disc, 0, args.ws_periods,
+                                      log=lambda m: print(m, file=sys.stderr, flush=True))]
     else:
         params = W.surrogate_params(args.ws_n, 2)
         rows = WS.evaluate(net, norm, params, 2, args.ws_periods,
                            log=lambda m: print(m, file=sys.stderr, flush=True))
     eval_s = time.time() - t1
     sm = WS.summarize(rows, args.ws_periods)
+    config = {"workload": disc.name if args.ws_target != "heldout" else f"surrogate_heldout_{args.ws_n}",
+              "training_steady_states": int(keep.sum()), "period_limit": args.ws_periods}
+    if args.ws_target == "heldout":
+        config.update(cells=128, steps_per_rf_period=1000, particles_per_species_initial=20000)
+    else:
+        config.update(cells=disc.n_cells, steps_per_rf_period=int(round(1.0 / (disc.rf_frequency_Hz * disc.dt_s))),
+                      particles_per_species_initial=disc.n_super[0])
     if args.ws_out:
         with open(args.ws_out, "w") as f:
             json.dump(dict(summary=sm, rows=rows), f, indent=1)
@@ -217,12 +230,7 @@ def run_warmstart(args, B, torch):
         "vs_baseline": None,
         "dtype": "f32 particles, bf16 network",
         "data": "synthetic",
-        "config": ({"workload": f"surrogate_heldout_{args.ws_n}", "training_steady_states": int(keep.sum()),
-                    "period_limit": args.ws_periods, "cells": 128, "steps_per_rf_period": 1000,
-                    "particles_per_species_initial": 20000} if args.ws_target == "heldout" else
-                   {"workload": "helium_2.5cm_512c_40Pa_200V", "training_steady_states": int(keep.sum()),
-                    "period_limit": args.ws_periods, "cells": 512, "steps_per_rf_period": 2000,
-                    "particles_per_species_initial": 1000000}),
+        "config": config,
         "summary": sm,
         "train_s": train_s,
         "train_loss": loss,
@@ -295,8 +303,9 @@ def main():
     ap.add_argument("--ws-n", type=int, default=16, help="warmstart: held-out discharges")
     ap.add_argument("--ws-periods", type=int, default=1500, help="warmstart: RF period limit")
     ap.add_argument("--ws-out", default=None, help="warmstart: write every discharge's result (JSON)")
-    ap.add_argument("--ws-target", default="heldout", choices=("heldout", "production"),
-                    help="warmstart: held-out draws of the training family, or the production discharge")
+    ap.add_argument("--ws-target", default="heldout", choices=("heldout", "production", "large"),
+                    help="warmstart: held-out draws of the training family, the production discharge, "
+                         "or the large one")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps of the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-blocks", type=int, default=0)

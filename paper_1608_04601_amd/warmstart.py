@@ -117,8 +117,9 @@ def period_profiles(view, disc):
 def run(discs, max_periods, warm=None, stream=None, log=None):
     """Advance the discharges (one batch) period by period; warm[k] (or None) holds the
     profiles (n_e, n_i, mean_energy_e, flux_i) that discharge k starts from.  Returns one
-    dict per discharge: steady_at, periods, final (the last W-period mean profiles),
-    alive (electrons and ions at the end), extinct."""
+    dict per discharge: steady_at, periods, final (the last W-period mean profiles), drift
+    (the criterion's profile change between the last two windows), alive (electrons and
+    ions at the end), extinct."""
     spp = {int(round(1.0 / (d.rf_frequency_Hz * d.dt_s))) for d in discs}
     if len(spp) != 1:
         raise ValueError("all discharges of a run need the same steps per RF period")
@@ -136,7 +137,7 @@ def run(discs, max_periods, warm=None, stream=None, log=None):
                 for k in range(len(discs))]
         for k in range(len(discs)):
             bt[k].moments(reset=True)
-        t0 = time.time()
+        t0 = t_log = time.time()
         for c in range(max_periods):
             if c % 50 == 49:
                 bt.rebalance()   # the counts drift while the discharges relax
@@ -149,15 +150,19 @@ def run(discs, max_periods, warm=None, stream=None, log=None):
                 born, lost = cnt["births_total"], int(cnt["absorbed_total"][1].sum())
                 det[k].add(period_profiles(bt[k], d), born - prev[k][0], lost - prev[k][1])
                 prev[k] = (born, lost)
-            if log and (c + 1) % 100 == 0:
+            if log and ((c + 1) % 100 == 0 or time.time() - t_log > 60.0):   # at least once a minute
+                t_log = time.time()
                 n_done = sum(x.done() for x in det)
-                log(f"  period {c + 1}: {n_done}/{len(discs)} steady, {time.time() - t0:.0f} s")
+                log(f"  period {c + 1}: {n_done}/{len(discs)} steady, {t_log - t0:.0f} s")
             if all(x.done() for x in det):
                 break
         out = []
         for k, d in enumerate(discs):
             cnt = bt[k].counters()
-            out.append(dict(steady_at=det[k].steady_at, periods=det[k].periods, final=det[k].window_mean(),
+            n, W = det[k].periods, det[k].W
+            drift = (profile_change(det[k].window_mean(n), det[k].window_mean(n - W)).tolist()
+                     if n >= 2 * W else None)   # change between the last two windows
+            out.append(dict(steady_at=det[k].steady_at, periods=n, final=det[k].window_mean(), drift=drift,
                             alive=tuple(cnt["n_alive"]), extinct=cnt["n_alive"][0] < 100))
         return out
     finally:
@@ -292,7 +297,8 @@ def evaluate_discharge(net, norm, disc, gas_id, max_periods, log=None):
     return dict(params=[float(v) for v in params[0]], cold_steady_at=cold["steady_at"], warm_steady_at=hot["steady_at"],
                 extinct=bool(cold["extinct"] or hot["extinct"]), warm_vs_cold=profile_change(hot["final"], cold["final"]).tolist(),
                 prediction_vs_cold=profile_change(pred, cold["final"]).tolist(), alive_cold=cold["alive"],
-                alive_warm=hot["alive"])
+                alive_warm=hot["alive"], periods_run=[cold["periods"], hot["periods"]],
+                drift_cold=cold["drift"], drift_warm=hot["drift"])
 
 
 def summarize(rows, max_periods):

@@ -76,3 +76,21 @@ def test_profile_change_is_relative_rms():
     b[2] *= 1.05
     ch = WS.profile_change(a, b)
     np.testing.assert_allclose(ch, [0, 0, 0.05 / 1.05, 0, 0], rtol=1e-12)
+
+
+def test_large_periodic_weight_matches_the_stored_steady_states():
+    """The large discharge's periodic-state weight: with the stored argon steady states
+    nearest 80 Pa, 300 V, 3 cm (mean n_e over the gap), the periodic state holds about
+    2.5e7 particles per species."""
+    import workloads as W
+    d = W.large_argon_periodic()
+    weight = d.n_init_m3 * d.gap_m / d.n_super[0]
+    data = np.load(WS.DATA_PATH)
+    P, prof = data["params"], data["profiles"]
+    argon = (P[:, 3] == 0) & ~data["extinct"]
+    dist = ((P[:, 0] - 80.0) / 70.0) ** 2 + ((P[:, 1] - 300.0) / 300.0) ** 2 + ((P[:, 2] - 0.03) / 0.01) ** 2
+    near = np.argsort(np.where(argon, dist, np.inf))[:3]
+    n_mean = np.mean([np.mean(prof[k, 0]) for k in near])   # stored n_e in m^-3
+    count = n_mean * d.gap_m / weight
+    assert 1.5e7 <= count <= 3.5e7, count
+    assert d.capacity[0] >= 1.5 * 2.5e7 and d.n_cells == 4096

@@ -173,6 +173,17 @@ def large_argon(seed: int = 0, n_super: int = 25_000_000) -> Discharge:
         processes=argon_like(top, top), sort_every=50, moments_every=1)
 
 
+def large_argon_periodic(seed: int = 0, n_periodic: int = 25_000_000) -> Discharge:
+    """The large argon discharge with the weight of its periodic state: that state's
+    cycle-averaged density is about 9.5e15 m^-3 (the stored steady states nearest 80 Pa,
+    300 V, 3 cm), so W = 9.5e15 d / n_periodic and the uniform start at 1e15 m^-3 holds
+    n_periodic / 9.5 particles per species; storage for 1.6 n_periodic."""
+    n0 = int(round(n_periodic * 1e15 / 9.5e15))
+    cap = int(1.6 * n_periodic)
+    return large_argon(seed=seed, n_super=n0).replace(name="argon_3cm_4096c_80Pa_300V_periodic_weight",
+                                                      capacity=(cap, cap), max_births_per_step=1 << 18)
+
+
 def sweep_argon(n_discharges: int = 64, seed: int = 0) -> Tuple[Discharge, ...]:
     """Pressure/voltage sweep of argon-like discharges drawn from default_rng(seed):
     p ~ U(10, 80) Pa, V0 ~ U(100, 400) V, d ~ U(2, 3) cm, cells ~ U{256..1024} rounded to
