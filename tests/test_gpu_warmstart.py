@@ -3,7 +3,7 @@ GPU (BF16 matrix cores) from the stored periodic states of 127 seed-1 discharges
 batched PIC produced, then two held-out seed-2 discharges run from a uniform start (the
 plain method) and from the predicted state, side by side in one batch.  Both must reach
 the steady-state criterion; the warm start in at most half the RF periods, and its final
-profiles within 3 % of the cold start's (the cold PIC run is the judge of the error)."""
+profiles within 3 % of the cold start's (the cold PIC run decides the error)."""
 import numpy as np
 import pytest
 
