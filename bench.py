@@ -178,14 +178,14 @@ def run_sweep(args, B, torch):
 def run_warmstart(args, B, torch):
     """RF periods to the periodic steady state, warm (surrogate) against cold (uniform)
     start: the network is trained on the GPU from stored steady states of the batched PIC
-    (seed-1 parameter draws), then held-out draws (seed 2) run cold and warm in one batch
+    (parameter draws of seeds 1 and 3), then held-out draws (seed 2) run cold and warm in one batch
     until the steady-state criterion holds (or the period limit)."""
     import numpy as np
 
     import workloads as W
     from paper_1608_04601_amd import warmstart as WS
     torch.cuda.set_device(0)
-    data = np.load(WS.DATA_PATH)
+    data = WS.load_data()
     keep = ~data["extinct"]
     t0 = time.time()
     net, norm, loss = WS.train(data["params"][keep], data["profiles"][keep], steps=4000)

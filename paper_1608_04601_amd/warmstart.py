@@ -34,6 +34,7 @@ Command line (run from the repository root on a GPU):
 """
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -41,14 +42,25 @@ import numpy as np
 
 from . import binding as B
 
-import os
-
-DATA_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "steady_states_seed1.npz")
+DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+DATA_PATH = os.path.join(DATA_DIR, "steady_states_seed1.npz")
+# training draws: seeds 1 and 3 (seed 2 is held out)
+DATA_PATHS = tuple(os.path.join(DATA_DIR, f"steady_states_seed{s}.npz") for s in (1, 3))
 N_POINTS = 128
 QUANTITIES = ("n_e", "n_i", "mean_energy_e", "phi", "flux_i")
 WIDTH, DEPTH = 256, 3
 DENSITY_FLOOR = 1e12
 FLUX_SCALE = 1e19
+
+
+def load_data(paths=None):
+    """The stored steady states of every training draw that is present, concatenated:
+    params, profiles, steady_at, periods, extinct, alive."""
+    paths = [p for p in (DATA_PATHS if paths is None else paths) if os.path.exists(p)]
+    if not paths:
+        raise FileNotFoundError("no stored steady states")
+    parts = [np.load(p) for p in paths]
+    return {k: np.concatenate([d[k] for d in parts]) for k in parts[0].files}
 
 
 # ------------------------------------------------------------------ steady state

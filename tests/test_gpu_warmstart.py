@@ -1,6 +1,6 @@
 """What the trained surrogate gains over the plain method: the network is trained on the
-GPU (BF16 matrix cores) from the stored periodic states of 127 seed-1 discharges that the
-batched PIC produced, then two held-out seed-2 discharges run from a uniform start (the
+GPU (BF16 matrix cores) from the stored periodic states of the training draws (seeds 1
+and 3) that the batched PIC produced, then two held-out seed-2 discharges run from a uniform start (the
 plain method) and from the predicted state, side by side in one batch.  Both must reach
 the steady-state criterion; the warm start in at most half the RF periods, and its final
 profiles within 3 % of the cold start's (the cold PIC run decides the error)."""
@@ -17,7 +17,7 @@ HELD_OUT = [6, 15]   # positions in the seed-2 draw of 16
 
 
 def test_warm_start_reaches_the_periodic_state_in_fewer_periods():
-    data = np.load(WS.DATA_PATH)
+    data = WS.load_data()
     keep = ~data["extinct"]
     net, norm, loss = WS.train(data["params"][keep], data["profiles"][keep], steps=4000)
     log(f"surrogate trained on {keep.sum()} periodic states: loss {loss:.3e}")

@@ -94,3 +94,17 @@ def test_large_periodic_weight_matches_the_stored_steady_states():
     count = n_mean * d.gap_m / weight
     assert 1.5e7 <= count <= 3.5e7, count
     assert d.capacity[0] >= 1.5 * 2.5e7 and d.n_cells == 4096
+
+
+def test_training_data_concatenates_the_stored_draws(tmp_path):
+    a = dict(params=np.zeros((2, 4)), profiles=np.zeros((2, 5, WS.N_POINTS)), extinct=np.array([False, True]))
+    b = dict(params=np.ones((3, 4)), profiles=np.ones((3, 5, WS.N_POINTS)), extinct=np.array([False] * 3))
+    pa, pb = str(tmp_path / "a.npz"), str(tmp_path / "b.npz")
+    np.savez(pa, **a)
+    np.savez(pb, **b)
+    d = WS.load_data([pa, str(tmp_path / "missing.npz"), pb])
+    assert d["params"].shape == (5, 4) and d["profiles"].shape == (5, 5, WS.N_POINTS)
+    assert d["extinct"].tolist() == [False, True, False, False, False]
+    assert np.all(d["params"][2:] == 1.0)
+    full = WS.load_data()
+    assert len(full["params"]) >= 128 and full["profiles"].shape[1:] == (5, WS.N_POINTS)
