@@ -1374,6 +1374,34 @@ __global__ void diag_nodes_kernel(Params P, DiagDev D) {
 // cnt[2 nc + b] alive particles of block b (compaction); cursor[] holds the matching
 // exclusive prefix sums.
 // ----------------------------------------------------------------------------------
+// Adds this wave's particles to the per-cell counts h (cell j, or -1 for a hole or an
+// inactive lane) with one LDS atomic per distinct cell instead of one per particle: a
+// cell-sorted wave holds one or two cells, and same-address atomics from the lanes of a
+// wave would be serialised.  Returns, per lane, the count of its cell before this wave's
+// first lane of that cell plus its rank among the wave's lanes of the cell (unused when
+// want_pos is false).  Every lane of the wave must call this.
+__device__ __forceinline__ unsigned wave_cell_add(unsigned* h, int j, bool want_pos) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long todo = __ballot(j >= 0);
+    unsigned pos = 0;
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const int jl = __shfl(j, leader, 64);
+        const unsigned long long same = __ballot(j == jl) & todo;
+        unsigned base = 0;
+        if (lane == leader) {
+            const unsigned got = atomicAdd(&h[jl], (unsigned)__popcll(same));
+            base = want_pos ? got : 0u;
+        }
+        base = (unsigned)__shfl((int)base, leader, 64);
+        if (j == jl) pos = base + (unsigned)__popcll(same & ((1ull << lane) - 1ull));
+        todo &= ~same;
+    }
+    return pos;
+}
+
+constexpr int kSortUnroll = 4;   // elements per thread per iteration of the reordering loops
+
 // Blocks [0, Ge) take contiguous electron ranges, [Ge, G) ion ranges (G >= 2 when both
 // species have slots).
 __device__ __forceinline__ void sort_split(int G, int b, int64_t ns0, int64_t ns1, int& s, int& Ge, int64_t& begin,
@@ -1410,20 +1438,38 @@ __device__ __forceinline__ void sort_count_body(const Params& P, unsigned* cnt, 
     for (int i = tid; i <= nc; i += nt) h[i] = 0;
     __syncthreads();
     const float* X = bufsel(P.x, cur, s);
+    // whole waves walk the range, kSortUnroll elements per thread with all loads issued first
     if (!P.sort_cells[s]) {
         unsigned c = 0;
-        for (int64_t v = begin + tid; v < end; v += nt) c += X[v] > 0.0f ? 1u : 0u;
+        for (int64_t vb = begin; vb < end; vb += kSortUnroll * nt) {
+            float x[kSortUnroll];
+#pragma unroll
+            for (int k = 0; k < kSortUnroll; ++k) {
+                const int64_t v = vb + k * nt + tid;
+                x[k] = v < end ? X[v] : -1.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < kSortUnroll; ++k) c += x[k] > 0.0f ? 1u : 0u;
+        }
         if (c) atomicAdd(&h[nc], c);
         __syncthreads();
         if (tid == 0) cnt[2 * nc + blk] = h[nc];
     } else {
-        for (int64_t v = begin + tid; v < end; v += nt) {
-            const float x = X[v];
-            if (x > 0.0f) {
-                int j;
-                float w;
-                cell_of(x, nc, j, w);
-                atomicAdd(&h[j], 1u);
+        for (int64_t vb = begin; vb < end; vb += kSortUnroll * nt) {
+            float x[kSortUnroll];
+#pragma unroll
+            for (int k = 0; k < kSortUnroll; ++k) {
+                const int64_t v = vb + k * nt + tid;
+                x[k] = v < end ? X[v] : -1.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < kSortUnroll; ++k) {
+                int j = -1;
+                if (x[k] > 0.0f) {
+                    float w;
+                    cell_of(x[k], nc, j, w);
+                }
+                wave_cell_add(h, j, false);
             }
         }
         __syncthreads();
@@ -1496,8 +1542,8 @@ __device__ __forceinline__ void sort_scatter_body(const Params& P, unsigned* cur
     const int lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
     unsigned* h = reinterpret_cast<unsigned*>(smem);   // nc local counts, then cursors
     unsigned* base = h + nc;                            // nc reserved bases
-    unsigned* wcnt = base + nc;                         // 16 wave counts
-    unsigned* flag = wcnt + 16;
+    unsigned* wcnt = base + nc;                         // kSortUnroll x 16 wave counts
+    unsigned* flag = wcnt + kSortUnroll * 16;
     Ctrl* C = P.ctrl;
     const unsigned cur = C->cur, nxt = cur ^ 1u;
     int s, Ge;
@@ -1515,43 +1561,75 @@ __device__ __forceinline__ void sort_scatter_body(const Params& P, unsigned* cur
     uint32_t* IDo = bufsel(P.id, nxt, s);
     if (!P.sort_cells[s]) {
         // order-keeping compaction: this range's alive particles go, in order, to
-        // [cursor[2 nc + b], ...)
+        // [cursor[2 nc + b], ...); kSortUnroll chunks of blockDim elements per pair of
+        // barriers, every load of the round issued first
         unsigned pos = cursor[2 * nc + blk];
-        for (int64_t vb = begin; vb < end; vb += nt) {
-            const int64_t v = vb + tid;
-            const float x = v < end ? X[v] : -1.0f;
-            const bool alive = x > 0.0f;
-            const unsigned long long m = __ballot(alive);
-            if (lane == 0) wcnt[wid] = (unsigned)__popcll(m);
-            __syncthreads();
-            unsigned off = 0, tot = 0;
-            for (int w = 0; w < nw; ++w) {
-                const unsigned c = wcnt[w];
-                off += w < wid ? c : 0u;
-                tot += c;
+        for (int64_t vb = begin; vb < end; vb += kSortUnroll * nt) {
+            float x[kSortUnroll], vx[kSortUnroll], vy[kSortUnroll], vz[kSortUnroll];
+            uint32_t id[kSortUnroll];
+            unsigned long long m[kSortUnroll];
+#pragma unroll
+            for (int k = 0; k < kSortUnroll; ++k) {
+                const int64_t v = vb + k * nt + tid;
+                const bool in = v < end;
+                x[k] = in ? X[v] : -1.0f;
+                vx[k] = in ? VX[v] : 0.0f;
+                vy[k] = in ? VY[v] : 0.0f;
+                vz[k] = in ? VZ[v] : 0.0f;
+                id[k] = in ? ID[v] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kSortUnroll; ++k) {
+                m[k] = __ballot(x[k] > 0.0f);
+                if (lane == 0) wcnt[k * 16 + wid] = (unsigned)__popcll(m[k]);
             }
             __syncthreads();
-            if (alive) {
-                const unsigned d = pos + off + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
-                Xo[d] = x;
-                VXo[d] = VX[v];
-                VYo[d] = VY[v];
-                VZo[d] = VZ[v];
-                IDo[d] = ID[v];
+            unsigned off[kSortUnroll], run = 0;
+#pragma unroll
+            for (int k = 0; k < kSortUnroll; ++k) {
+                unsigned before = 0, tot = 0;
+                for (int w = 0; w < nw; ++w) {
+                    const unsigned c = wcnt[k * 16 + w];
+                    before += w < wid ? c : 0u;
+                    tot += c;
+                }
+                off[k] = pos + run + before;
+                run += tot;
             }
-            pos += tot;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kSortUnroll; ++k) {
+                if (x[k] > 0.0f) {
+                    const unsigned d = off[k] + (unsigned)__popcll(m[k] & ((1ull << lane) - 1ull));
+                    Xo[d] = x[k];
+                    VXo[d] = vx[k];
+                    VYo[d] = vy[k];
+                    VZo[d] = vz[k];
+                    IDo[d] = id[k];
+                }
+            }
+            pos += run;
         }
     } else {
-        // cell sort: this block reserves, per cell, room after the blocks before it
+        // cell sort: this block reserves, per cell, room after the blocks before it; whole
+        // waves walk the range, and a wave's particles of one cell take consecutive places
         for (int i = tid; i < nc; i += nt) h[i] = 0;
         __syncthreads();
-        for (int64_t v = begin + tid; v < end; v += nt) {
-            const float x = X[v];
-            if (x > 0.0f) {
-                int j;
-                float w;
-                cell_of(x, nc, j, w);
-                atomicAdd(&h[j], 1u);
+        for (int64_t vb = begin; vb < end; vb += kSortUnroll * nt) {
+            float x[kSortUnroll];
+#pragma unroll
+            for (int k = 0; k < kSortUnroll; ++k) {
+                const int64_t v = vb + k * nt + tid;
+                x[k] = v < end ? X[v] : -1.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < kSortUnroll; ++k) {
+                int j = -1;
+                if (x[k] > 0.0f) {
+                    float w;
+                    cell_of(x[k], nc, j, w);
+                }
+                wave_cell_add(h, j, false);
             }
         }
         __syncthreads();
@@ -1561,18 +1639,35 @@ __device__ __forceinline__ void sort_scatter_body(const Params& P, unsigned* cur
             h[i] = 0;
         }
         __syncthreads();
-        for (int64_t v = begin + tid; v < end; v += nt) {
-            const float x = X[v];
-            if (x > 0.0f) {
-                int j;
-                float w;
-                cell_of(x, nc, j, w);
-                const unsigned d = base[j] + atomicAdd(&h[j], 1u);
-                Xo[d] = x;
-                VXo[d] = VX[v];
-                VYo[d] = VY[v];
-                VZo[d] = VZ[v];
-                IDo[d] = ID[v];
+        for (int64_t vb = begin; vb < end; vb += 2 * nt) {
+            float x[2], vx[2], vy[2], vz[2];
+            uint32_t id[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int64_t v = vb + k * nt + tid;
+                const bool in = v < end;
+                x[k] = in ? X[v] : -1.0f;
+                vx[k] = in ? VX[v] : 0.0f;
+                vy[k] = in ? VY[v] : 0.0f;
+                vz[k] = in ? VZ[v] : 0.0f;
+                id[k] = in ? ID[v] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                int j = -1;
+                if (x[k] > 0.0f) {
+                    float w;
+                    cell_of(x[k], nc, j, w);
+                }
+                const unsigned r = wave_cell_add(h, j, true);
+                if (j >= 0) {
+                    const unsigned d = base[j] + r;
+                    Xo[d] = x[k];
+                    VXo[d] = vx[k];
+                    VYo[d] = vy[k];
+                    VZo[d] = vz[k];
+                    IDo[d] = id[k];
+                }
             }
         }
     }
@@ -1763,7 +1858,7 @@ hipError_t launch_sort(const Params& P, unsigned* cnt, unsigned* cursor, int blo
     hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(1024), 0, st, P, cnt, cursor, blocks);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds_scatter = (size_t)2 * P.n_cells * sizeof(unsigned) + 17 * sizeof(unsigned);
+    const size_t lds_scatter = (size_t)2 * P.n_cells * sizeof(unsigned) + (kSortUnroll * 16 + 1) * sizeof(unsigned);
     hipLaunchKernelGGL(sort_scatter_kernel, dim3(blocks), dim3(threads), lds_scatter, st, P, cursor);
     return hipGetLastError();
 }
@@ -1778,7 +1873,7 @@ hipError_t launch_sort_batch(const Params* batch, const int* sseg, int nd, int b
     hipLaunchKernelGGL(sort_scan_batch_kernel, dim3(nd), dim3(1024), 0, st, batch, sseg);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds_scatter = (size_t)2 * max_cells * sizeof(unsigned) + 17 * sizeof(unsigned);
+    const size_t lds_scatter = (size_t)2 * max_cells * sizeof(unsigned) + (kSortUnroll * 16 + 1) * sizeof(unsigned);
     hipLaunchKernelGGL(sort_scatter_batch_kernel, dim3(blocks), dim3(1024), lds_scatter, st, batch, sseg, nd);
     return hipGetLastError();
 }
