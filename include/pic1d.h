@@ -332,6 +332,12 @@ int pic_batch_rebalance(pic_batch* b);
 /* Number of graph replays since the last pic_batch_set_graph (for tests). */
 int pic_batch_graph_launches(const pic_batch* b, int64_t* n);
 
+/* Test hook: pic_set_record_decisions for every discharge of the batch, so that batched
+ * launches write the per-slot collision decisions that pic_get_decisions reads through
+ * pic_batch_handle.  Completes pending steps and drops any captured graph; allocates the
+ * records on first use. */
+int pic_batch_set_record_decisions(pic_batch* b, int on);
+
 /* Launch and reordering schedule chosen by pic_batch_autotune. */
 typedef struct pic_tuning {
     int32_t threads;         /* workgroup size of the batched particle pass */

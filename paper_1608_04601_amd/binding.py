@@ -22,7 +22,7 @@ EXPORTED = ("pic_init", "pic_step", "pic_sync", "pic_moments", "pic_free", "pic_
             "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
             "pic_batch_free", "pic_batch_last_error", "pic_batch_timing", "pic_batch_set_graph",
             "pic_batch_graph_launches", "pic_batch_autotune", "pic_batch_rebalance",
-            "pic_load_profiles", "pic_diag_config", "pic_diag_sample", "pic_diag_read", "pic_electrode_fluxes",
+            "pic_batch_set_record_decisions", "pic_load_profiles", "pic_diag_config", "pic_diag_sample", "pic_diag_read", "pic_electrode_fluxes",
             "mlp_init", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_gradient",
             "mlp_train_step", "mlp_free", "mlp_last_error")
 
@@ -143,6 +143,7 @@ def load_library(path: str = None):
         "pic_batch_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
         "pic_batch_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
         "pic_batch_rebalance": (C.c_int, [C.c_void_p]),
+        "pic_batch_set_record_decisions": (C.c_int, [C.c_void_p, C.c_int]),
         "pic_load_profiles": (C.c_int, [H, C.c_int32, dp, dp, dp, dp]),
         "pic_diag_config": (C.c_int, [H, C.c_int32, C.c_double]),
         "pic_diag_sample": (C.c_int, [H]),
@@ -403,6 +404,10 @@ class Batch:
     def rebalance(self):
         """Split the workgroups anew by the particles alive now."""
         _check_batch(self.b, load_library().pic_batch_rebalance(self.b))
+
+    def record_decisions(self, on: bool):
+        """Test hook: batched launches write the per-slot collision decisions."""
+        _check_batch(self.b, load_library().pic_batch_set_record_decisions(self.b, int(bool(on))))
 
     def graph_launches(self):
         n = C.c_int64()

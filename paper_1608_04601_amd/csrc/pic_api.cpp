@@ -1049,6 +1049,7 @@ struct pic_batch {
     bool gpend = false;
     hipStream_t cap = nullptr;   // private stream the graph is captured on
     int64_t graph_launches = 0;
+    bool record = false;         // batched launches write the decision records (test hook)
 };
 
 namespace {
@@ -1110,7 +1111,8 @@ int batch_launch(pic_batch* b, int mode) {
             if (hipEventRecord(ea, b->stream) != hipSuccess) return bfail(b, PIC_EHIP, "hipEventRecord");
         }
     }
-    const hipError_t e = pic::launch_pass_batch(mode, b->dparams, b->dseg, (int)b->hs.size(), b->seg.back(),
+    const int m = mode | ((b->record && (mode & pic::kComplete)) ? pic::kRecord : 0);
+    const hipError_t e = pic::launch_pass_batch(m, b->dparams, b->dseg, (int)b->hs.size(), b->seg.back(),
                                                 b->threads, b->lds, b->stream);
     if (e != hipSuccess) return bfail(b, PIC_EHIP, std::string("batched pass launch: ") + hipGetErrorString(e));
     if (eb) {
@@ -1369,6 +1371,23 @@ int pic_batch_rebalance(pic_batch* b) {
     }
     const hipError_t e = batch_layout(b, b->threads, b->rounds, w);
     if (e != hipSuccess) return bfail(b, PIC_EHIP, std::string("batch layout: ") + hipGetErrorString(e));
+    return PIC_OK;
+}
+
+int pic_batch_set_record_decisions(pic_batch* b, int on) {
+    if (!b) return PIC_EINVAL;
+    if (pic_batch_sync(b)) return b->status;
+    for (pic_handle* h : b->hs)
+        if (pic_set_record_decisions(h, on)) return batch_status(b);
+    std::vector<pic::Params> hp;
+    for (pic_handle* h : b->hs) hp.push_back(h->P);
+    if (hipMemcpy(b->dparams, hp.data(), sizeof(pic::Params) * hp.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return bfail(b, PIC_EHIP, "parameter upload");
+    if (b->gexec) {   // the captured launches carry the old mode
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    b->record = on != 0;
     return PIC_OK;
 }
 

@@ -1775,6 +1775,14 @@ hipError_t launch_pass(int mode, const Params& P, int blocks, int threads, size_
 hipError_t launch_pass_batch(int mode, const Params* batch, const int* seg, int nd, int blocks, int threads,
                              size_t lds, hipStream_t st) {
     switch (mode) {
+        case kComplete | kAdvance | kRecord:
+            hipLaunchKernelGGL(pass_batch_kernel<kComplete | kAdvance | kRecord>, dim3(blocks), dim3(threads), lds,
+                               st, batch, seg, nd);
+            break;
+        case kComplete | kRecord:
+            hipLaunchKernelGGL(pass_batch_kernel<kComplete | kRecord>, dim3(blocks), dim3(threads), lds, st, batch,
+                               seg, nd);
+            break;
         case kComplete | kAdvance:
             hipLaunchKernelGGL(pass_batch_kernel<kComplete | kAdvance>, dim3(blocks), dim3(threads), lds, st, batch, seg,
                                nd);
@@ -1805,6 +1813,12 @@ hipError_t set_pass_batch_lds_limit(size_t bytes) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_batch_kernel<kComplete>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_batch_kernel<kComplete | kAdvance | kRecord>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_batch_kernel<kComplete | kRecord>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e == hipSuccess) limit = bytes;
     return e;

@@ -36,3 +36,49 @@ def vth(o, s):
     from oracle.constants import E0
     T = (o.cfg.te_init_eV, o.cfg.ti_init_eV)[s]
     return np.sqrt(E0 * max(T, 1e-3) / o.d.m[s])
+
+
+def compare_decisions(o, s, decisions, next_id_before):
+    """Candidates identical; process choices identical outside the margin band.  Returns the
+    GPU's choice per candidate id and the ids whose choice legitimately differs."""
+    rec = o.last[f"mcc{s}"]
+    did, dcode = decisions
+    old = did.astype(np.int64) < next_id_before
+    did, dcode = did[old].astype(np.int64), dcode[old]
+    cand_gpu = np.sort(did[dcode >= 1])
+    order = np.argsort(rec["candidates"].astype(np.int64), kind="stable")
+    cand_orc = rec["candidates"].astype(np.int64)[order]
+    assert np.array_equal(cand_gpu, cand_orc), (s, len(cand_gpu), len(cand_orc))
+    gmap = dict(zip(did.tolist(), dcode.tolist()))
+    g_sel = np.array([gmap[i] - 2 if gmap[i] >= 2 else -1 for i in cand_orc.tolist()], dtype=np.int64)
+    o_sel = rec["selected"][order]
+    differ = g_sel != o_sel
+    excused = rec["margin"][order] < MARGIN * o.d.numax[s]
+    assert np.all(excused[differ]), (s, int(differ.sum()), int((differ & ~excused).sum()))
+    return dict(zip(cand_orc.tolist(), g_sel.tolist())), set(cand_orc[differ].tolist())
+
+
+def compare_species(o, s, g_after, unsure, skip_ids_from, disc):
+    """Per-id state after one step; ids in `unsure` and ids >= skip_ids_from are skipped."""
+    S = o.state(s)
+    gid = g_after["id"].astype(np.int64)
+    oid = S["id"].astype(np.int64)
+    gid_c = gid[gid < skip_ids_from]
+    oid_c = oid[oid < skip_ids_from]
+    # the same particles survive (absorption ties at FP32 resolution excepted)
+    only_g = np.setdiff1d(gid_c, oid_c)
+    only_o = np.setdiff1d(oid_c, gid_c)
+    assert len(only_g) + len(only_o) <= 2, (s, only_g[:5], only_o[:5])
+    common, ig, io = np.intersect1d(gid, oid, return_indices=True)
+    keep = np.array([(i not in unsure) and i < skip_ids_from for i in common.tolist()], dtype=bool)
+    ig, io = ig[keep], io[keep]
+    dx = np.abs(g_after["x"][ig] - S["x"][io])
+    assert dx.max(initial=0) <= REL_X * disc.gap_m, (s, dx.max())
+    vt = vth(o, s)
+    for key in ("vx", "vy", "vz"):
+        ref = S[key][io]
+        dv = np.abs(g_after[key][ig] - ref)
+        lim = REL_V * np.maximum(np.abs(ref), vt)
+        bad = dv > lim
+        assert not bad.any(), (s, key, int(bad.sum()), float((dv / lim).max()))
+    return len(ig)

@@ -142,6 +142,7 @@ def test_new_entry_points_reject_null_on_host():
     L = B.load_library()
     for f, args in ((L.pic_batch_set_graph, (None, 10)), (L.pic_batch_autotune, (None, 10, None)),
                     (L.pic_batch_rebalance, (None,)), (L.pic_batch_timing, (None, 1, None, None)),
+                    (L.pic_batch_set_record_decisions, (None, 1)),
                     (L.pic_diag_config, (None, 10, 20.0)), (L.pic_diag_sample, (None,)),
                     (L.pic_diag_read, (None, None, 0)), (L.pic_electrode_fluxes, (None, 10, None, None)),
                     (L.pic_load_profiles, (None, 3, None, None, None, None))):

@@ -155,3 +155,64 @@ def test_autotune_choice_is_valid_and_keeps_results():
         with B.Discharge(d) as solo:
             solo.step(steps)
             _same(got[k], _state(solo), k)
+
+
+def _sweep_members():
+    """Three discharges of the sweep's kind (argon-like, T_rf/2000, uneven sizes and grids);
+    the middle one has the sweep's shape and is the one checked against the oracle."""
+    sw = W.sweep_argon()
+    checked = W.sweep_argon(1, seed=5)[0].replace(n_cells=576, n_super=(120_000, 120_000),
+                                                  capacity=(480_000, 480_000), name="sweep_checked")
+    return [sw[3], checked, sw[7]]
+
+
+def test_batch_member_single_step_parity_against_oracle():
+    """A member of sweep shape (576 cells, 1.2e5 particles per species) advanced by batched
+    launches in the batch's own launch shape.  Its state is handed to the FP64 oracle and
+    both take one step: the drift, deposit and solve run in the batched advancing launch, the
+    MCC and births in the batched completing launch, with decision records on.  Checked as
+    in the single-discharge protocol: fields, per-id positions and velocities, candidate
+    sets, process choices outside the margin band, ionisation-product ids."""
+    from gpu_common import REL_FIELD, compare_decisions, compare_species, oracle_input
+    from oracle import Oracle
+    discs = _sweep_members()
+    k = 1
+    disc = discs[k]
+    with B.Batch(discs) as bt:
+        log(f"batch member parity: {disc.n_cells} cells, {disc.n_super[0]} per species, "
+            f"batch blocks {[bt.blocks(q) for q in range(len(bt))]}")
+        bt.record_decisions(True)
+        for done in (0, 60):
+            bt.step(60)
+            bt.sync()                  # batched completing launch: nothing is left pending
+            v = bt[k]
+            c0 = v.counters()
+            o = Oracle(disc, load=False)
+            o.set_state(c0["step"], oracle_input(v, c0))
+            bt.step(1)                 # batched advancing launch
+            bt.sync()                  # batched completing launch (MCC, births)
+            o.step()
+            c1 = v.counters()
+            f = v.fields()
+            assert c1["step"] == c0["step"] + 1
+            assert np.max(np.abs(f["E"] - o.E)) <= REL_FIELD * np.abs(o.E).max()
+            assert np.max(np.abs(f["phi"] - o.phi)) <= REL_FIELD * max(np.abs(o.phi).max(), disc.rf_voltage_V)
+            choice, unsure = {}, [set(), set()]
+            for s in (0, 1):
+                ch, unsure[s] = compare_decisions(o, s, B.pic_get_decisions(v.h, s), c0["next_id"][s])
+                choice.update({(s, i): j for i, j in ch.items()})
+            iz = [j for j, p in enumerate(disc.processes) if p.kind == W.E_IONIZATION]
+            g_par = {i for (s, i), j in choice.items() if s == 0 and j in iz}
+            o_par = set(o.last["births"]["parent"].astype(np.int64).tolist())
+            assert (g_par ^ o_par) <= unsure[0]
+            same_births = g_par == o_par
+            if same_births:
+                assert c1["next_id"] == (o.sp[0].next_id, o.sp[1].next_id)
+            n_cand = sum(len(o.last[f"mcc{s}"]["candidates"]) for s in (0, 1))
+            for s in (0, 1):
+                skip = 1 << 62 if same_births else c0["next_id"][s]
+                n_cmp = compare_species(o, s, v.particles(s), unsure[s], skip, disc)
+                assert n_cmp > 0.99 * len(o.sp[s].x) - len(unsure[s]) - 4
+            log(f"  step {c0['step']}->{c1['step']}: {n_cand} candidates, {len(o_par)} births, "
+                f"excused choices {len(unsure[0]) + len(unsure[1])}")
+        assert v.counters()["numax_violations"] == (0, 0)

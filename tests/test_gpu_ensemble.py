@@ -1,9 +1,13 @@
 """Statistical parity: cycle-averaged profiles of the GPU path against the FP64 oracle's
-ensemble (small argon-like discharge, seeds 0..7, RF cycles 10..20 of a cold start).
+ensemble (small argon-like discharge, RF cycles 10..20 of a cold start).
 
-The oracle's numbers come from tests/golden/make_ensemble.py (oracle only).  At every node
-|mu_gpu - mu_oracle| <= max(0.03 max|mu_oracle|, 2 sqrt(s_gpu^2/8 + s_oracle^2/8)); the mean
-electron energy is compared only where n_e >= 1e-3 max n_e (it is undefined in the sheaths).
+The oracle's runs (seeds 0..7) come from tests/golden/make_ensemble.py (oracle only).  The
+GPU runs use seeds 100..115, disjoint from those: the two ensembles share no initial load
+and no collision draw (the draws are keyed by seed, id and step), so they are independent
+samples of the same process, as the 2-sigma rule assumes.  At every node
+|mu_gpu - mu_oracle| <= max(0.03 max|mu_oracle|, 2 sqrt(s_gpu^2/n_gpu + s_oracle^2/n_oracle));
+the mean electron energy is compared only where n_e >= 1e-3 max n_e (it is undefined in the
+sheaths).
 """
 import json
 import os
@@ -19,6 +23,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "argon_small_ensemble.json")
 KEYS = ("n_e", "n_i", "mean_energy_e", "flux_i", "phi")
+GPU_SEEDS = tuple(range(100, 116))
 
 
 def _arr(v):
@@ -32,7 +37,8 @@ def test_cycle_averaged_profiles_match_oracle_ensemble():
     orc = {k: np.stack([_arr(r[k]) for r in doc["runs"]]) for k in KEYS}
     gpu = {k: [] for k in KEYS}
     scal = {"J0": [], "flux_i_powered": []}
-    for seed in doc["seeds"]:
+    assert not set(GPU_SEEDS) & set(doc["seeds"])
+    for seed in GPU_SEEDS:
         disc = W.small_argon(seed=seed)
         spp = disc.steps_per_period
         log(f"ensemble seed {seed}")
@@ -48,12 +54,12 @@ def test_cycle_averaged_profiles_match_oracle_ensemble():
         scal["J0"].append(m["J0"])
         scal["flux_i_powered"].append(m["flux_i_powered"])
     gpu = {k: np.stack(v) for k, v in gpu.items()}
-    n = len(doc["seeds"])
+    ng, no = len(GPU_SEEDS), len(doc["seeds"])
     ne_mask = np.nanmean(orc["n_e"], 0) >= 1e-3 * np.nanmax(np.nanmean(orc["n_e"], 0))
     for k in KEYS:
         mg, mo = np.nanmean(gpu[k], 0), np.nanmean(orc[k], 0)
         sg, so = np.nanstd(gpu[k], 0, ddof=1), np.nanstd(orc[k], 0, ddof=1)
-        tol = np.maximum(0.03 * np.nanmax(np.abs(mo)), 2 * np.sqrt(sg ** 2 / n + so ** 2 / n))
+        tol = np.maximum(0.03 * np.nanmax(np.abs(mo)), 2 * np.sqrt(sg ** 2 / ng + so ** 2 / no))
         sel = ne_mask if k == "mean_energy_e" else np.ones_like(mo, bool)
         bad = (np.abs(mg - mo) > tol) & sel
         log(f"  {k}: max |dmu|/tol = {np.nanmax(np.abs(mg - mo)[sel] / tol[sel]):.3f}")
@@ -61,6 +67,6 @@ def test_cycle_averaged_profiles_match_oracle_ensemble():
     for k, vals in scal.items():
         mo = np.array([r[k] for r in doc["runs"]])
         mg = np.array(vals)
-        tol = max(0.03 * abs(mo.mean()), 2 * np.sqrt(mg.var(ddof=1) / n + mo.var(ddof=1) / n))
+        tol = max(0.03 * abs(mo.mean()), 2 * np.sqrt(mg.var(ddof=1) / ng + mo.var(ddof=1) / no))
         log(f"  {k}: gpu {mg.mean():.4g} oracle {mo.mean():.4g} tol {tol:.3g}")
         assert abs(mg.mean() - mo.mean()) <= tol, k

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_common import MARGIN, REL_FIELD, REL_V, REL_X, log, oracle_input, vth
+from gpu_common import REL_FIELD, compare_decisions, compare_species, log, oracle_input
 from oracle import Oracle, derive
 from paper_1608_04601_amd import binding as B
 
@@ -88,52 +88,6 @@ def test_initial_load_matches_oracle():
         assert np.allclose(f["Q"], o.Q, rtol=0, atol=1e-6 * np.abs(o.Q).max())
 
 
-def _compare_decisions(o, s, decisions, next_id_before):
-    """Candidates identical; process choices identical outside the margin band.  Returns the
-    GPU's choice per candidate id and the ids whose choice legitimately differs."""
-    rec = o.last[f"mcc{s}"]
-    did, dcode = decisions
-    old = did.astype(np.int64) < next_id_before
-    did, dcode = did[old].astype(np.int64), dcode[old]
-    cand_gpu = np.sort(did[dcode >= 1])
-    order = np.argsort(rec["candidates"].astype(np.int64), kind="stable")
-    cand_orc = rec["candidates"].astype(np.int64)[order]
-    assert np.array_equal(cand_gpu, cand_orc), (s, len(cand_gpu), len(cand_orc))
-    gmap = dict(zip(did.tolist(), dcode.tolist()))
-    g_sel = np.array([gmap[i] - 2 if gmap[i] >= 2 else -1 for i in cand_orc.tolist()], dtype=np.int64)
-    o_sel = rec["selected"][order]
-    differ = g_sel != o_sel
-    excused = rec["margin"][order] < MARGIN * o.d.numax[s]
-    assert np.all(excused[differ]), (s, int(differ.sum()), int((differ & ~excused).sum()))
-    return dict(zip(cand_orc.tolist(), g_sel.tolist())), set(cand_orc[differ].tolist())
-
-
-def _compare_species(o, s, g_after, unsure, skip_ids_from, disc):
-    """Per-id state after one step; ids in `unsure` and ids >= skip_ids_from are skipped."""
-    S = o.state(s)
-    gid = g_after["id"].astype(np.int64)
-    oid = S["id"].astype(np.int64)
-    gid_c = gid[gid < skip_ids_from]
-    oid_c = oid[oid < skip_ids_from]
-    # the same particles survive (absorption ties at FP32 resolution excepted)
-    only_g = np.setdiff1d(gid_c, oid_c)
-    only_o = np.setdiff1d(oid_c, gid_c)
-    assert len(only_g) + len(only_o) <= 2, (s, only_g[:5], only_o[:5])
-    common, ig, io = np.intersect1d(gid, oid, return_indices=True)
-    keep = np.array([(i not in unsure) and i < skip_ids_from for i in common.tolist()], dtype=bool)
-    ig, io = ig[keep], io[keep]
-    dx = np.abs(g_after["x"][ig] - S["x"][io])
-    assert dx.max(initial=0) <= REL_X * disc.gap_m, (s, dx.max())
-    vt = vth(o, s)
-    for key in ("vx", "vy", "vz"):
-        ref = S[key][io]
-        dv = np.abs(g_after[key][ig] - ref)
-        lim = REL_V * np.maximum(np.abs(ref), vt)
-        bad = dv > lim
-        assert not bad.any(), (s, key, int(bad.sum()), float((dv / lim).max()))
-    return len(ig)
-
-
 @pytest.mark.parametrize("case", list(CASES))
 def test_single_step_parity(case):
     disc = CASES[case]()
@@ -167,11 +121,17 @@ def test_single_step_parity(case):
             # fields at t_{k+1}
             assert np.max(np.abs(f["E"] - o.E)) <= REL_FIELD * np.abs(o.E).max()
             assert np.max(np.abs(f["phi"] - o.phi)) <= REL_FIELD * max(np.abs(o.phi).max(), disc.rf_voltage_V)
-            assert np.isclose(c1["J_last"], o.J, rtol=1e-4, atol=1e-6 * abs(o.J) + 1e-9)
+            # J is a difference quotient, eps0 (E_0^{n+1} - E_0^n) / dt, of two FP64 fields
+            # whose charges differ only by the FP32 rounding of the positions (random, about
+            # 1e-7 relative per node); measured agreement is about 1e-6, within the 1e-5
+            # single-step contract
+            rel_J = abs(c1["J_last"] - o.J) / max(abs(o.J), 1e-30)
+            log(f"    J: gpu {c1['J_last']:.6g} oracle {o.J:.6g} rel {rel_J:.2e}")
+            assert np.isclose(c1["J_last"], o.J, rtol=1e-5, atol=1e-9)
             # decisions, then births: the ionising parents agree except for excused choices
             choice, unsure = {}, [set(), set()]
             for s in (0, 1):
-                ch, unsure[s] = _compare_decisions(o, s, B.pic_get_decisions(d.h, s), c0["next_id"][s])
+                ch, unsure[s] = compare_decisions(o, s, B.pic_get_decisions(d.h, s), c0["next_id"][s])
                 choice.update({(s, i): j for i, j in ch.items()})
             iz = [j for j, p in enumerate(disc.processes) if p.kind == W.E_IONIZATION]
             g_par = {i for (s, i), j in choice.items() if s == 0 and j in iz}
@@ -187,7 +147,7 @@ def test_single_step_parity(case):
             for s in (0, 1):
                 # products keep comparable ids only when the parent sets agree
                 skip = 1 << 62 if same_births else c0["next_id"][s]
-                n_cmp = _compare_species(o, s, g[s], unsure[s], skip, disc)
+                n_cmp = compare_species(o, s, g[s], unsure[s], skip, disc)
                 assert n_cmp > 0.99 * len(o.sp[s].x) - len(unsure[s]) - 4
             # absorption counts per electrode
             ab = c1["absorbed_total"] - c0["absorbed_total"]
