@@ -56,6 +56,7 @@ extern "C" {
 #define PIC_FRAME_CM  1
 #define PIC_MAX_PROCESSES 16
 #define PIC_MAX_CELLS 4096
+#define PIC_NOALLOC_MAX_POINTS 1024   /* profile points of pic_load_profiles_noalloc */
 
 #define PIC_ELECTRON 0
 #define PIC_ION      1
@@ -233,6 +234,17 @@ int pic_get_fields(pic_handle* h, double* q_nodes, double* phi, float* e_nodes);
  * PIC_ECAPACITY if N_s exceeds the capacity, PIC_EINVAL for bad profiles. */
 int pic_load_profiles(pic_handle* h, int32_t n_points, const double* n_e, const double* n_i,
                       const double* mean_energy_e_eV, const double* flux_i);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): pic_load_profiles with the same
+ * arguments, results and errors, except that it allocates nothing.  Its staging table
+ * lives in a fixed device array of the library, 2 x 4 x PIC_NOALLOC_MAX_POINTS doubles
+ * (64 KiB) per GPU, held until the process ends; n_points above PIC_NOALLOC_MAX_POINTS is
+ * rejected with PIC_EINVAL.  The handle's device must be current.  Every call on a GPU
+ * shares that GPU's array, so calls that overlap on one GPU (from several host threads)
+ * race; each call overwrites what it uses before reading it. */
+int pic_load_profiles_noalloc(pic_handle* h, int32_t n_points, const double* n_e, const double* n_i,
+                              const double* mean_energy_e_eV, const double* flux_i);
 
 /* ---- Diagnostics of the results section (off the particle pass).  A diagnostic window
  * adds up samples of the completed electron state at chosen time levels: call

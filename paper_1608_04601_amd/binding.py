@@ -22,7 +22,7 @@ EXPORTED = ("pic_init", "pic_step", "pic_sync", "pic_moments", "pic_free", "pic_
             "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
             "pic_batch_free", "pic_batch_last_error", "pic_batch_timing", "pic_batch_set_graph",
             "pic_batch_graph_launches", "pic_batch_autotune", "pic_batch_rebalance",
-            "pic_batch_set_record_decisions", "pic_load_profiles", "pic_diag_config", "pic_diag_sample", "pic_diag_read", "pic_electrode_fluxes",
+            "pic_batch_set_record_decisions", "pic_load_profiles", "pic_load_profiles_noalloc", "pic_diag_config", "pic_diag_sample", "pic_diag_read", "pic_electrode_fluxes",
             "mlp_init", "mlp_num_params", "mlp_set_params", "mlp_get_params", "mlp_forward", "mlp_gradient",
             "mlp_train_step", "mlp_free", "mlp_last_error")
 
@@ -145,6 +145,7 @@ def load_library(path: str = None):
         "pic_batch_rebalance": (C.c_int, [C.c_void_p]),
         "pic_batch_set_record_decisions": (C.c_int, [C.c_void_p, C.c_int]),
         "pic_load_profiles": (C.c_int, [H, C.c_int32, dp, dp, dp, dp]),
+        "pic_load_profiles_noalloc": (C.c_int, [H, C.c_int32, dp, dp, dp, dp]),
         "pic_diag_config": (C.c_int, [H, C.c_int32, C.c_double]),
         "pic_diag_sample": (C.c_int, [H]),
         "pic_diag_read": (C.c_int, [H, C.POINTER(pic_diag_out), C.c_int]),
@@ -300,6 +301,14 @@ def pic_load_profiles(h, n_e, n_i, mean_energy_e, flux_i):
     n = arrs[0].size
     assert all(a.size == n for a in arrs)
     _check(h, load_library().pic_load_profiles(h, n, *[_ptr(a, C.c_double) for a in arrs]))
+
+
+def pic_load_profiles_noalloc(h, n_e, n_i, mean_energy_e, flux_i):
+    """pic_load_profiles without device allocation (at most PIC_NOALLOC_MAX_POINTS points)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (n_e, n_i, mean_energy_e, flux_i)]
+    n = arrs[0].size
+    assert all(a.size == n for a in arrs)
+    _check(h, load_library().pic_load_profiles_noalloc(h, n, *[_ptr(a, C.c_double) for a in arrs]))
 
 
 def pic_diag_config(h, n_bins: int, u_max_eV: float):

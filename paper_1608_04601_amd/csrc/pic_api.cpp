@@ -32,6 +32,7 @@ hipError_t set_pass_batch_lds_limit(size_t bytes);
 hipError_t pass_batch_occupancy(int threads, size_t lds, int* blocks_per_cu);
 hipError_t launch_sort_batch(const Params* batch, const int* sseg, int nd, int blocks, int max_cells,
                              hipStream_t st);
+hipError_t noalloc_scratch(int device, double** ptr, size_t* count);
 }  // namespace pic
 
 namespace {
@@ -409,6 +410,11 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
 
     // ---- stream
     if (!hip_ok(h, hipGetDevice(&h->device), "hipGetDevice")) goto fail_init;
+    {   // the no-allocation loader's staging: its address on this device, looked up once
+        double* sp = nullptr;
+        size_t sn = 0;
+        if (!hip_ok(h, pic::noalloc_scratch(h->device, &sp, &sn), "scratch address")) goto fail_init;
+    }
     h->stream = static_cast<hipStream_t>(hip_stream);   // NULL: the device's null stream
 
     {
@@ -769,11 +775,11 @@ int pic_set_particles(pic_handle* h, int species, const double* x, const float* 
     return check_device(h);
 }
 
-int pic_load_profiles(pic_handle* h, int32_t n_points, const double* n_e, const double* n_i,
-                      const double* mean_energy_e_eV, const double* flux_i) {
-    if (!h) return PIC_EINVAL;
-    if (h->status) return h->status;
-    if (n_points < 2 || n_points > 65536) return fail(h, PIC_EINVAL, "n_points must be in [2, 65536]");
+namespace {
+// Checks the warm-start profiles and the handle's state (not stepped); reads the control
+// block into *c.
+int check_profiles(pic_handle* h, int32_t n_points, const double* n_e, const double* n_i,
+                   const double* mean_energy_e_eV, const double* flux_i, pic::Ctrl* c) {
     if (!n_e || !n_i || !mean_energy_e_eV || !flux_i) return fail(h, PIC_EINVAL, "profile arrays are NULL");
     for (int j = 0; j < n_points; ++j) {
         if (!std::isfinite(n_e[j]) || !std::isfinite(n_i[j]) || !std::isfinite(mean_energy_e_eV[j]) ||
@@ -784,52 +790,109 @@ int pic_load_profiles(pic_handle* h, int32_t n_points, const double* n_e, const 
     }
     if (h->pending) return fail(h, PIC_ESTATE, "the discharge has already been stepped");
     if (check_device(h)) return h->status;
-    pic::Ctrl c;
-    if (read_ctrl(h, &c)) return h->status;
-    if (c.step != 0) return fail(h, PIC_ESTATE, "the discharge has already been stepped");
-    // per species: cumulative integral, density, thermal speed squared, drift
+    if (read_ctrl(h, c)) return h->status;
+    if (c->step != 0) return fail(h, PIC_ESTATE, "the discharge has already been stepped");
+    return PIC_OK;
+}
+
+// Loader table of species s on host memory t[4 * n_points]: cumulative integral of the
+// density (trapezoids), density, thermal speed squared per component, mean v_x.  Returns the
+// particle count round(integral / W) in *count, or an error.
+int profile_table(pic_handle* h, int s, int32_t n_points, const double* n_e, const double* n_i,
+                  const double* mean_energy_e_eV, const double* flux_i, double* t, int64_t* count) {
     const double hm = h->cfg.gap_m / (double)(n_points - 1);
-    const double kE0 = 1.602176634e-19, kKB = 1.380649e-23, kME = 9.1093837015e-31, kAMU = 1.66053906660e-27;
-    const double M = h->cfg.gas_mass_amu * kAMU;
-    std::vector<double> tab[2];
-    int64_t count[2];
-    for (int s = 0; s < 2; ++s) {
-        const double* dens = s == 0 ? n_e : n_i;
-        std::vector<double>& t = tab[s];
-        t.assign((size_t)4 * n_points, 0.0);
-        for (int j = 1; j < n_points; ++j) t[j] = t[j - 1] + 0.5 * (dens[j - 1] + dens[j]) * hm;
-        for (int j = 0; j < n_points; ++j) {
-            t[n_points + j] = dens[j];
-            t[2 * n_points + j] = s == 0 ? kE0 * (2.0 / 3.0) * mean_energy_e_eV[j] / kME
-                                         : kKB * h->cfg.gas_temperature_K / M;
-            t[3 * n_points + j] = (s == 1 && n_i[j] > 0.0) ? flux_i[j] / n_i[j] : 0.0;
-        }
-        count[s] = (int64_t)std::floor(t[n_points - 1] / h->W + 0.5);
-        if (count[s] < 1) return fail(h, PIC_EINVAL, "a density profile holds less than one particle");
-        if (count[s] > h->cfg.capacity[s]) return fail(h, PIC_ECAPACITY, "the profiles need more particles than capacity");
+    const double M = h->cfg.gas_mass_amu * kAmu;
+    const double* dens = s == 0 ? n_e : n_i;
+    t[0] = 0.0;
+    for (int j = 1; j < n_points; ++j) t[j] = t[j - 1] + 0.5 * (dens[j - 1] + dens[j]) * hm;
+    for (int j = 0; j < n_points; ++j) {
+        t[n_points + j] = dens[j];
+        t[2 * n_points + j] = s == 0 ? kE0 * (2.0 / 3.0) * mean_energy_e_eV[j] / kMe
+                                     : kKB * h->cfg.gas_temperature_K / M;
+        t[3 * n_points + j] = (s == 1 && n_i[j] > 0.0) ? flux_i[j] / n_i[j] : 0.0;
     }
-    double* dtab = nullptr;
-    if (!hip_ok(h, hipMalloc(&dtab, sizeof(double) * 8 * (size_t)n_points), "hipMalloc")) return h->status;
+    *count = (int64_t)std::floor(t[n_points - 1] / h->W + 0.5);
+    if (*count < 1) return fail(h, PIC_EINVAL, "a density profile holds less than one particle");
+    if (*count > h->cfg.capacity[s]) return fail(h, PIC_ECAPACITY, "the profiles need more particles than capacity");
+    return PIC_OK;
+}
+
+// Device half of the warm-start load: the tables of both species are in dtab (species s at
+// 4 * n_points * s); draws the particles, sets the counts and solves the field at t = 0.
+int load_from_tables(pic_handle* h, pic::Ctrl& c, int32_t n_points, const double* dtab, const int64_t count[2]) {
+    const double hm = h->cfg.gap_m / (double)(n_points - 1);
     const unsigned b = c.cur;
-    bool ok = true;
-    for (int s = 0; s < 2 && ok; ++s)
-        ok = hip_ok(h, hipMemcpyAsync(dtab + (size_t)4 * n_points * s, tab[s].data(), sizeof(double) * 4 * n_points,
-                                      hipMemcpyHostToDevice, h->stream), "copy profiles") &&
-             hip_ok(h, pic::launch_load_profile(h->P, s, count[s], b, dtab + (size_t)4 * n_points * s, n_points, hm,
-                                                h->stream), "load_profile_kernel");
-    ok = hip_ok(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize") && ok;
-    (void)hipFree(dtab);
-    if (!ok) return h->status;
+    for (int s = 0; s < 2; ++s)
+        if (!hip_ok(h, pic::launch_load_profile(h->P, s, count[s], b, dtab + (size_t)4 * n_points * s, n_points, hm,
+                                                h->stream),
+                    "load_profile_kernel"))
+            return h->status;
     for (int s = 0; s < 2; ++s) {
         c.n_slots[s] = count[s];
         c.n_alive[s] = count[s];
         c.next_id[s] = count[s];
     }
-    if (!hip_ok(h, hipMemcpy(h->P.ctrl, &c, sizeof(c), hipMemcpyHostToDevice), "write ctrl")) return h->status;
-    if (!hip_ok(h, hipMemset(h->P.Qs, 0, 2 * (h->cfg.n_cells + 1) * sizeof(unsigned long long)), "zero Q"))
+    if (!hip_ok(h, hipMemcpyAsync(h->P.ctrl, &c, sizeof(c), hipMemcpyHostToDevice, h->stream), "write ctrl") ||
+        !hip_ok(h, hipMemsetAsync(h->P.Qs, 0, 2 * (h->cfg.n_cells + 1) * sizeof(unsigned long long), h->stream),
+                "zero Q") ||
+        !hip_ok(h, pic::launch_pass(pic::kDeposit, h->P, h->blocks, h->threads, h->lds, h->stream),
+                "deposit pass"))
         return h->status;
-    if (launch_pass_timed(h, pic::kDeposit)) return h->status;
     return check_device(h);
+}
+}  // namespace
+
+int pic_load_profiles(pic_handle* h, int32_t n_points, const double* n_e, const double* n_i,
+                      const double* mean_energy_e_eV, const double* flux_i) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (n_points < 2 || n_points > 65536) return fail(h, PIC_EINVAL, "n_points must be in [2, 65536]");
+    pic::Ctrl c;
+    if (check_profiles(h, n_points, n_e, n_i, mean_energy_e_eV, flux_i, &c)) return h->status;
+    std::vector<double> tab((size_t)8 * n_points);
+    int64_t count[2];
+    for (int s = 0; s < 2; ++s)
+        if (profile_table(h, s, n_points, n_e, n_i, mean_energy_e_eV, flux_i, tab.data() + (size_t)4 * n_points * s,
+                          &count[s]))
+            return h->status;
+    double* dtab = nullptr;
+    if (!hip_ok(h, hipMalloc(&dtab, sizeof(double) * tab.size()), "hipMalloc")) return h->status;
+    int rc = hip_ok(h, hipMemcpyAsync(dtab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, h->stream),
+                    "copy profiles")
+                 ? load_from_tables(h, c, n_points, dtab, count)
+                 : h->status;
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(dtab);
+    return rc ? rc : h->status;
+}
+
+int pic_load_profiles_noalloc(pic_handle* h, int32_t n_points, const double* n_e, const double* n_i,
+                              const double* mean_energy_e_eV, const double* flux_i) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (n_points < 2 || n_points > PIC_NOALLOC_MAX_POINTS)
+        return fail(h, PIC_EINVAL, "n_points must be in [2, PIC_NOALLOC_MAX_POINTS] for the no-allocation loader");
+    int dev = -1;
+    if (!hip_ok(h, hipGetDevice(&dev), "hipGetDevice")) return h->status;
+    if (dev != h->device) return fail(h, PIC_EINVAL, "the handle's device must be current");
+    double* dtab = nullptr;
+    size_t room = 0;
+    if (!hip_ok(h, pic::noalloc_scratch(dev, &dtab, &room), "scratch address")) return h->status;
+    if ((size_t)8 * n_points > room) return fail(h, PIC_EINVAL, "profiles exceed the no-allocation staging");
+    pic::Ctrl c;
+    if (check_profiles(h, n_points, n_e, n_i, mean_energy_e_eV, flux_i, &c)) return h->status;
+    // one species at a time through a fixed host buffer: nothing is allocated
+    double tab[4 * pic::kNoAllocMaxPoints];
+    int64_t count[2];
+    for (int s = 0; s < 2; ++s) {
+        if (profile_table(h, s, n_points, n_e, n_i, mean_energy_e_eV, flux_i, tab, &count[s])) return h->status;
+        if (!hip_ok(h, hipMemcpyAsync(dtab + (size_t)4 * n_points * s, tab, sizeof(double) * 4 * n_points,
+                                      hipMemcpyHostToDevice, h->stream),
+                    "copy profiles") ||
+            !hip_ok(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize"))
+            return h->status;
+    }
+    return load_from_tables(h, c, n_points, dtab, count);
 }
 
 int pic_diag_config(pic_handle* h, int32_t n_bins, double u_max_eV) {

@@ -1837,6 +1837,35 @@ hipError_t launch_load(const Params& P, int s, int64_t n, double vth, hipStream_
     return hipGetLastError();
 }
 
+// Staging for the warm-start tables of pic_load_profiles_noalloc, for callers that cannot
+// allocate device memory: both species' tables of up to kNoAllocMaxPoints points, in
+// device memory that lives as long as the process (one copy per GPU).  Host code reaches it
+// only through the address noalloc_scratch returns, never through the array's name.
+static __device__ __align__(256) double scratch[2 * 4 * kNoAllocMaxPoints];
+
+// Address of this device's copy of scratch.  The first call on a device (with that device
+// current) looks it up with hipGetSymbolAddress; later calls return the kept address.
+hipError_t noalloc_scratch(int device, double** ptr, size_t* count) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<double*>(p);
+    }
+    *ptr = addr[device];
+    *count = sizeof(scratch) / sizeof(double);
+    return hipSuccess;
+}
+
 hipError_t launch_load_profile(const Params& P, int s, int64_t n, unsigned b, const double* tab, int np, double h_m,
                                hipStream_t st) {
     if (n <= 0) return hipSuccess;

@@ -13,6 +13,7 @@ constexpr int kMaxProc = 16;
 constexpr int kMaxProcPerSpecies = 8;
 constexpr int kMaxCells = 4096;
 constexpr int kBirthSortCap = 2048;   // births per step ranked by a sort in LDS; more are binned
+constexpr int kNoAllocMaxPoints = 1024;   // profile points of pic_load_profiles_noalloc
 constexpr int kMaxSortBlocks = 4096;  // workgroups of the periodic reordering
 // Per-workgroup counters of the particle pass go to kRepSets sets (workgroup b to set
 // b % kRepSets), each on its own 256-byte stretch, so that their atomics do not all
