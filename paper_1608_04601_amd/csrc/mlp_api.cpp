@@ -262,6 +262,23 @@ int mlp_get_params(mlp_handle* h, float* host, int64_t n) {
 int mlp_forward(mlp_handle* h, const float* x, int64_t batch, float* y) {
     if (check_ready(h)) return h ? h->status : PIC_EINVAL;
     if (!x || !y || batch < 1) return mfail(h, PIC_EINVAL, "x or y is NULL, or batch < 1");
+    if (mlp::fused_forward_supported(h->n_in, h->width, n_layers(h))) {
+        // one launch for every layer; the same products and roundings as the GEMM path
+        mlp::FusedArgs a{};
+        a.x = x;
+        a.y = y;
+        a.batch = batch;
+        a.n_in = h->n_in;
+        a.width = h->width;
+        a.layers = n_layers(h);
+        a.n_out = h->n_out;
+        for (int l = 0; l < a.layers; ++l) {
+            a.W[l] = h->pb + h->w_off[l];
+            a.bias[l] = h->p + h->b_off[l];
+        }
+        if (!mok(h, mlp::launch_forward_fused(a, h->stream), "fused forward launch")) return h->status;
+        return PIC_OK;
+    }
     for (int64_t b0 = 0; b0 < batch; b0 += h->max_batch) {
         const int64_t nb = std::min<int64_t>(h->max_batch, batch - b0);
         if (!mok(h, mlp::launch_to_bf16(x + b0 * h->n_in, h->act[0], nb * h->n_in, h->stream), "convert"))

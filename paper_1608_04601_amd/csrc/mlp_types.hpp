@@ -28,6 +28,22 @@ struct GemmArgs {
 
 constexpr int kColPartsHost = 64;   // partial sums per column of launch_colsum
 
+// The whole forward pass in one launch (inference): every layer for a tile of samples per
+// workgroup, activations kept in LDS.  Supported shapes: n_in <= 32, width a multiple of 32
+// and <= kFusedMaxWidth, at most kFusedMaxLayers affine layers.
+constexpr int kFusedMaxWidth = 256;
+constexpr int kFusedMaxLayers = 8;
+struct FusedArgs {
+    const float* x;            // [batch x n_in] FP32
+    float* y;                  // [batch x n_out] FP32
+    int64_t batch;
+    int n_in, width, layers, n_out;
+    const uint16_t* W[kFusedMaxLayers];   // BF16 weights of layer l, [out x in]
+    const float* bias[kFusedMaxLayers];   // FP32 biases of layer l
+};
+bool fused_forward_supported(int n_in, int width, int layers);
+hipError_t launch_forward_fused(const FusedArgs& a, hipStream_t st);
+
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 hipError_t launch_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t st);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t st);

@@ -933,8 +933,9 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
 #pragma unroll
         for (int r = 0; r < kEpiNodesPerThread; ++r) {
             const int i = tid + r * nt;
-            q0[r] = i < nn ? ld_agent(&P.Qs[i]) : 0ull;
-            q1[r] = i < nn ? ld_agent(&P.Qs[nn + i]) : 0ull;
+            q0[r] = i < nn ? __hip_atomic_exchange(&P.Qs[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+            q1[r] = i < nn ? __hip_atomic_exchange(&P.Qs[nn + i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : 0ull;
         }
         const double scale = kQScaleInv * P.e0W;
 #pragma unroll
@@ -1001,8 +1002,6 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
         const bool next_sampled = (MODE & kAdvance) && ((step + 1) % P.moments_every == 0);
         for (int i = tid; i < nn; i += nt) {
             P.Q_last[i] = Qd[i];
-            P.Qs[i] = 0ull;
-            P.Qs[nn + i] = 0ull;
             if (next_sampled) {
                 unsafeAtomicAdd(&P.mom[i], dep0[i]);
                 unsafeAtomicAdd(&P.mom[nn + i], dep1[i]);

@@ -21,7 +21,11 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = {"surrogate_4x256x3x640": (4, 256, 3, 640, 512), "ragged_5x70x2x33": (5, 70, 2, 33, 77),
           # batch 2048: the weight gradients split K over several workgroups
-          "surrogate_batch2048": (4, 256, 3, 640, 2048)}
+          "surrogate_batch2048": (4, 256, 3, 640, 2048),
+          # the one-launch forward pass: a batch that is not a multiple of its 64-sample
+          # tile, and a wider input with a narrower network (width 70 above takes the
+          # layer-by-layer products)
+          "surrogate_batch1001": (4, 256, 3, 640, 1001), "fused_20x64x2x40": (20, 64, 2, 40, 300)}
 
 
 def _data(n_in, n_out, batch, seed):
