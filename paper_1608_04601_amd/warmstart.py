@@ -63,6 +63,12 @@ def load_data(paths=None):
     return {k: np.concatenate([d[k] for d in parts]) for k in parts[0].files}
 
 
+def training_mask(data):
+    """The draws whose stored profiles are periodic steady states: not extinct, and the
+    steady-state criterion met (draws still drifting at the period limit are left out)."""
+    return ~data["extinct"] & (data["steady_at"] >= 0)
+
+
 # ------------------------------------------------------------------ steady state
 def profile_change(a, b):
     """Per quantity: RMS of a - b over the grid, relative to the larger max |.| of a, b."""
@@ -126,12 +132,13 @@ def period_profiles(view, disc):
     return np.array(prof)
 
 
-def run(discs, max_periods, warm=None, stream=None, log=None):
+def run(discs, max_periods, warm=None, stream=None, log=None, max_seconds=None):
     """Advance the discharges (one batch) period by period; warm[k] (or None) holds the
-    profiles (n_e, n_i, mean_energy_e, flux_i) that discharge k starts from.  Returns one
-    dict per discharge: steady_at, periods, final (the last W-period mean profiles), drift
-    (the criterion's profile change between the last two windows), alive (electrons and
-    ions at the end), extinct."""
+    profiles (n_e, n_i, mean_energy_e, flux_i) that discharge k starts from.  Stops when
+    every discharge is steady, after max_periods, or once max_seconds have passed.  Returns
+    one dict per discharge: steady_at, periods, final (the last W-period mean profiles),
+    drift (the criterion's profile change between the last two windows), alive (electrons
+    and ions at the end), extinct."""
     spp = {int(round(1.0 / (d.rf_frequency_Hz * d.dt_s))) for d in discs}
     if len(spp) != 1:
         raise ValueError("all discharges of a run need the same steps per RF period")
@@ -167,6 +174,10 @@ def run(discs, max_periods, warm=None, stream=None, log=None):
                 n_done = sum(x.done() for x in det)
                 log(f"  period {c + 1}: {n_done}/{len(discs)} steady, {t_log - t0:.0f} s")
             if all(x.done() for x in det):
+                break
+            if max_seconds is not None and time.time() - t0 > max_seconds:
+                if log:
+                    log(f"  stopped after {c + 1} periods at the {max_seconds:.0f} s limit")
                 break
         out = []
         for k, d in enumerate(discs):
@@ -263,8 +274,8 @@ def cmd_generate(a):
 
 def cmd_train(a):
     data = np.load(a.data)
-    keep = ~data["extinct"]
-    _log(f"train: {keep.sum()} steady states (extinct ones left out)")
+    keep = training_mask(data)
+    _log(f"train: {keep.sum()} steady states (extinct draws and draws not steady at the limit left out)")
     net, norm, loss = train(data["params"][keep], data["profiles"][keep], steps=a.steps, seed=a.seed, log=_log)
     np.savez(a.out, theta=net.get_params(), mu=norm["mu"], sd=norm["sd"], loss=loss,
              shape=np.array([4, WIDTH, DEPTH, 5 * N_POINTS]))
@@ -299,12 +310,12 @@ def evaluate(net, norm, params, seed, max_periods, log=None, index=None):
     return rows
 
 
-def evaluate_discharge(net, norm, disc, gas_id, max_periods, log=None):
+def evaluate_discharge(net, norm, disc, gas_id, max_periods, log=None, max_seconds=None):
     """One discharge of any fidelity, cold and warm in one batch.  The network sees its
     (p, V0, d, gas id); the prediction is resampled onto the loader's points."""
     params = np.array([[disc.pressure_Pa, disc.rf_voltage_V, disc.gap_m, float(gas_id)]])
     pred = predict(net, norm, params)[0]
-    res = run([disc, disc], max_periods, warm=[None, warm_profiles(pred)], log=log)
+    res = run([disc, disc], max_periods, warm=[None, warm_profiles(pred)], log=log, max_seconds=max_seconds)
     cold, hot = res
     return dict(params=[float(v) for v in params[0]], cold_steady_at=cold["steady_at"], warm_steady_at=hot["steady_at"],
                 extinct=bool(cold["extinct"] or hot["extinct"]), warm_vs_cold=profile_change(hot["final"], cold["final"]).tolist(),
@@ -316,15 +327,17 @@ def evaluate_discharge(net, norm, disc, gas_id, max_periods, log=None):
 def summarize(rows, max_periods):
     ok = [r for r in rows if not r["extinct"]]
     both = [r for r in ok if r["cold_steady_at"] is not None and r["warm_steady_at"] is not None]
-    cold = [r["cold_steady_at"] if r["cold_steady_at"] is not None else max_periods for r in ok]
-    warm = [r["warm_steady_at"] if r["warm_steady_at"] is not None else max_periods for r in ok]
+    # a run that is not steady counts with the periods it ran (a lower bound: the period
+    # limit, or fewer when a time limit stopped it)
+    cold = [r["cold_steady_at"] if r["cold_steady_at"] is not None else r["periods_run"][0] for r in ok]
+    warm = [r["warm_steady_at"] if r["warm_steady_at"] is not None else r["periods_run"][1] for r in ok]
     acc = [max(r["warm_vs_cold"]) for r in both]
     return dict(discharges=len(rows), extinct=len(rows) - len(ok), steady_both=len(both),
                 cold_periods_mean=float(np.mean(cold)) if cold else None,
                 warm_periods_mean=float(np.mean(warm)) if warm else None,
                 cold_not_steady=sum(r["cold_steady_at"] is None for r in ok),
                 warm_not_steady=sum(r["warm_steady_at"] is None for r in ok),
-                warm_faster=sum(w < c for w, c in zip(warm, cold)),
+                warm_faster=sum(r["warm_steady_at"] is not None and w < c for r, w, c in zip(ok, warm, cold)),
                 warm_vs_cold_max=float(max(acc)) if acc else None,
                 warm_vs_cold_median=float(np.median(acc)) if acc else None,
                 within_3pct=sum(a <= 0.03 for a in acc),

@@ -18,7 +18,7 @@ HELD_OUT = [6, 15]   # positions in the seed-2 draw of 16
 
 def test_warm_start_reaches_the_periodic_state_in_fewer_periods():
     data = WS.load_data()
-    keep = ~data["extinct"]
+    keep = WS.training_mask(data)
     net, norm, loss = WS.train(data["params"][keep], data["profiles"][keep], steps=4000)
     log(f"surrogate trained on {keep.sum()} periodic states: loss {loss:.3e}")
     params = W.surrogate_params(16, 2)[HELD_OUT]

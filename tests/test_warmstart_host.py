@@ -108,3 +108,14 @@ def test_training_data_concatenates_the_stored_draws(tmp_path):
     assert np.all(d["params"][2:] == 1.0)
     full = WS.load_data()
     assert len(full["params"]) >= 128 and full["profiles"].shape[1:] == (5, WS.N_POINTS)
+
+
+def test_training_uses_only_steady_states():
+    """Only draws that met the steady-state criterion are training targets: extinct draws
+    and draws still drifting at the period limit (steady_at = -1) are left out."""
+    d = dict(extinct=np.array([False, True, False, False]), steady_at=np.array([120, 300, -1, 0]))
+    assert WS.training_mask(d).tolist() == [True, False, False, True]
+    full = WS.load_data()
+    m = WS.training_mask(full)
+    assert np.all(full["steady_at"][m] >= 0) and not np.any(full["extinct"][m])
+    assert m.sum() < (~full["extinct"]).sum()   # some stored draws were still drifting
