@@ -1,7 +1,8 @@
 """Parity at full size, in the launch configuration bench.py times (automatic workgroup
 count, no decision recording): the production discharge (1e6 particles per species, 512
 cells) and the large one (2.5e7 per species, 4096 cells).  From the GPU's own state at step
-40, the oracle takes the whole state through one step.
+100 (after reorderings: every 20 and every 50 steps respectively), the oracle takes the
+whole state through one step.
 
 * The field of that state (deposit and Poisson) agrees within 1e-5 of its maximum.
 * After the step: fields within 1e-5; every particle's position within 1e-5 d (positions
@@ -27,7 +28,7 @@ def test_full_size_single_step(name):
     disc = CASES[name]()
     log(f"full-size parity: {name} N={disc.n_super} cells={disc.n_cells}")
     with B.Discharge(disc) as d:
-        d.step(40)
+        d.step(100)
         c0 = d.counters()
         o = Oracle(disc, load=False)
         o.set_state(c0["step"], oracle_input(d, c0))

@@ -162,15 +162,17 @@ def production_helium(seed: int = 0, n_super: int = 1_000_000) -> Discharge:
 
 def large_argon(seed: int = 0, n_super: int = 25_000_000) -> Discharge:
     """Large single discharge: argon-like, 80 Pa, 300 V, 3 cm, 4096 cells, 2.5e7 particles
-    per species, dt = T_rf/4000.  Reordered every 20 steps, so that any 20 consecutive steps
-    hold exactly one reordering (the reordering does not change results)."""
+    per species, dt = T_rf/4000.  Reordered every 50 steps (any 50 consecutive steps hold
+    exactly one reordering; the reordering does not change results).  Measured wall time per
+    step against the interval: 0.456 ms at 10, 0.432 at 20, 0.427 at 25, 0.416 at 50, 0.413 at
+    100: past 50 the pass gains less from cell order than the reordering costs."""
     top = _table_top(300.0)
     return Discharge(
         name="argon_3cm_4096c_80Pa_300V", gap_m=0.03, pressure_Pa=80.0, gas_temperature_K=300.0,
         gas_mass_amu=AMU_AR, rf_voltage_V=300.0, rf_frequency_Hz=F_RF, dt_s=1.0 / (F_RF * 4000),
         n_cells=4096, n_init_m3=1e15, te_init_eV=2.0, ti_init_eV=0.026,
         n_super=(n_super, n_super), capacity=(2 * n_super, 2 * n_super), seed=seed,
-        processes=argon_like(top, top), sort_every=20, moments_every=1)
+        processes=argon_like(top, top), sort_every=50, moments_every=1)
 
 
 def large_argon_periodic(seed: int = 0, n_periodic: int = 25_000_000) -> Discharge:
