@@ -110,12 +110,12 @@ bool hip_ok(pic_handle* h, hipError_t e, const char* what) {
 
 // Dynamic LDS of the particle pass for nn nodes and nt threads: the larger of the
 // streaming layout (counters, fixed-point deposit, fixed-point moment sum, field,
-// null-collision bounds, candidate queues of 128 three-word entries per wave) and the
+// null-collision bounds, candidate queues of 128 seven-word entries per wave) and the
 // epilogue layout (control block copy, three FP64 node arrays, scratch, then the
 // potential or, before the solve, the birth keys and parents).
 size_t pass_lds_bytes(int nn, int nt) {
     const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 8 + 4) + (size_t)(pic::kNullBins + 1) * 4 +
-                            (size_t)(nt / 64) * 128 * 3 * 4;
+                            (size_t)(nt / 64) * 128 * 7 * 4;
     const size_t epi_lds = 512 + (size_t)24 * nn + 512 + std::max((size_t)8 * nn, (size_t)pic::kBirthSortCap * 8);
     return std::max(pass_lds, epi_lds);
 }

@@ -136,9 +136,16 @@ struct Lds {
     unsigned long long* M;   // fixed-point second moment quantity
     float* E;
     float* U;                // kNullBins + 1
+    // collision candidate queues: the candidate's slot and its state as the stream loaded
+    // it (v_x completed), so that the MCC reads nothing back from memory (v_y, v_z of ions,
+    // which the stream does not load, excepted)
     uint32_t* qslot;
     uint32_t* qr;            // second Philox word of the collision draw
     float* qvx;              // completed v_x
+    float* qx;
+    uint32_t* qid;
+    float* qvy;              // electrons only
+    float* qvz;
 };
 
 // After the drift of an ionisation product: absorb at the electrodes (Sec. 2.5, ties
@@ -410,17 +417,24 @@ __device__ __forceinline__ bool stream_particle(const Params& P, const Lds& L, i
     return false;
 }
 
-// Null-collision MCC of one queued candidate (Sec. 2.5), then finish it.
+// Null-collision MCC of queue entry e (Sec. 2.5), then finish it.
 template <int MODE, int S>
-__device__ __forceinline__ void collide_entry(const Params& P, const Lds& L, int64_t i, float vx, uint32_t rword,
-                                              uint32_t stepf, unsigned cur, int64_t ns0, int64_t ns1, bool sample,
-                                              float& tq, float& tm, float& m2) {
-    // the queue keeps the slot, the completed v_x and the second Philox word; the rest of
-    // the state is still unchanged in memory
-    const float x = bufsel(P.x, cur, S)[i];
-    const uint32_t pid = bufsel(P.id, cur, S)[i];
-    float vy = bufsel(P.vy, cur, S)[i];
-    float vz = bufsel(P.vz, cur, S)[i];
+__device__ __forceinline__ void collide_entry(const Params& P, const Lds& L, unsigned e, uint32_t stepf,
+                                              unsigned cur, int64_t ns0, int64_t ns1, bool sample, float& tq,
+                                              float& tm, float& m2) {
+    const int64_t i = (int64_t)L.qslot[e];
+    float vx = L.qvx[e];
+    const uint32_t rword = L.qr[e];
+    const float x = L.qx[e];
+    const uint32_t pid = L.qid[e];
+    float vy, vz;
+    if (S == 0) {
+        vy = L.qvy[e];
+        vz = L.qvz[e];
+    } else {   // unchanged in memory
+        vy = bufsel(P.vy, cur, S)[i];
+        vz = bufsel(P.vz, cur, S)[i];
+    }
     int j;
     float w;
     cell_of(x, P.n_cells, j, w);
@@ -554,8 +568,7 @@ __device__ __forceinline__ void drain_queue(const Params& P, const Lds& L, int w
     wave_fence();
     if (lane < count) {
         const unsigned e = wq + n - count + lane;
-        collide_entry<MODE, S>(P, L, (int64_t)L.qslot[e], L.qvx[e], L.qr[e], stepf, cur, ns0, ns1, sample, tq, tm,
-                               m2);
+        collide_entry<MODE, S>(P, L, e, stepf, cur, ns0, ns1, sample, tq, tm, m2);
     }
     deposit_direct(L, P.n_cells, tq);
     if (sample) moment_direct(P, L, S, tm, m2);
@@ -617,6 +630,12 @@ __device__ __forceinline__ void process_particle(const Params& P, const Lds& L, 
                 L.qslot[e] = (uint32_t)i;
                 L.qr[e] = rw;
                 L.qvx[e] = r.vx;
+                L.qx[e] = r.x;
+                L.qid[e] = r.id;
+                if (S == 0) {
+                    L.qvy[e] = r.vy;
+                    L.qvz[e] = r.vz;
+                }
             }
             nq += (unsigned)__popcll(qm);
             if (nq >= 64u) {
@@ -1083,6 +1102,10 @@ __device__ __forceinline__ void pass_body(const Params& P, unsigned char* smem, 
     L.qslot = reinterpret_cast<uint32_t*>(L.U + kNullBins + 1);
     L.qr = L.qslot + qcap;
     L.qvx = reinterpret_cast<float*>(L.qr + qcap);
+    L.qx = L.qvx + qcap;
+    L.qid = reinterpret_cast<uint32_t*>(L.qx + qcap);
+    L.qvy = reinterpret_cast<float*>(L.qid + qcap);
+    L.qvz = L.qvy + qcap;
 
     const int64_t step = C->step;
     const unsigned cur = C->cur;
