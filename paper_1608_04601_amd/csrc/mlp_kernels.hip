@@ -390,16 +390,19 @@ unsigned grid_for(int64_t n, int threads) {
 
 // ----------------------------------------------------------------------------------
 // The forward pass in one launch.  A workgroup of four waves takes kFT samples and runs
-// every layer on them; the activations stay in LDS (two BF16 buffers, ping-pong) and never
-// reach HBM, so the pass reads the FP32 input and writes the FP32 output only.  A layer's
-// product is split over the waves by 64-column slices of its output; a wave computes all
-// kFT rows of its slice as 4 x 4 MFMA blocks (v_mfma_f32_16x16x32_bf16, K in steps of 32, in
-// order, as the layer-by-layer GEMMs do), with its A operands read from LDS and its B
-// operands (weight rows, K contiguous) straight from memory, where every workgroup finds
-// them in L2.  Hidden layers add the bias, apply ReLU and round to BF16 into the other LDS
-// buffer; the last layer adds the bias and stores FP32.
+// every layer on them; the activations stay in LDS (one BF16 buffer) and never reach HBM,
+// so the pass reads the FP32 input and writes the FP32 output only.  A layer's product is
+// split over the waves by 64-column slices of its output; a wave computes all kFT rows of
+// its slice as 8 x 4 MFMA blocks (v_mfma_f32_16x16x32_bf16, K in steps of 32, in order, as
+// the layer-by-layer GEMMs do), with its A operands read from LDS and its B operands
+// (weight rows, K contiguous) straight from memory, where every workgroup finds them in
+// L2; the next K step's weights are loaded while the current step multiplies.  Each
+// weight load thus serves kFT = 128 rows.  A hidden layer (at most 256 columns: one slice
+// per wave) keeps its results in registers until every wave has read the layer input,
+// then writes ReLU(acc + bias) rounded to BF16 over that input; the last layer adds the
+// bias and stores FP32.
 // ----------------------------------------------------------------------------------
-constexpr int kFT = 64;                          // samples per workgroup
+constexpr int kFT = 128;                         // samples per workgroup
 constexpr int kFLd = kFusedMaxWidth + 8;         // LDS row stride (BF16), 16-byte aligned rows
 
 bool fused_forward_supported(int n_in, int width, int layers) {
@@ -407,81 +410,108 @@ bool fused_forward_supported(int n_in, int width, int layers) {
            layers <= kFusedMaxLayers;
 }
 
-__global__ void __launch_bounds__(256) forward_fused_kernel(FusedArgs a) {
-    __shared__ __align__(16) uint16_t act[2][kFT * kFLd];
+namespace {
+// B operands of one K step for the four 16-column blocks from column nc: lane holds
+// W[n][kk .. kk + 7] of n = nc + 16 j + lane % 16 (zero past N or past the row's end).
+__device__ __forceinline__ void load_b_step(const uint16_t* Wl, int Kw, int N, int nc, int kk, bool short_rows,
+                                            bf16x8* bv) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int n = nc + 16 * j + (lane & 15);
+        if (short_rows) {   // layer 0 (n_in < 8 possible): element by element
+            uint16_t h[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) h[i] = (n < N && kk + i < Kw) ? Wl[(int64_t)n * Kw + kk + i] : (uint16_t)0;
+            bv[j] = *reinterpret_cast<const bf16x8*>(h);
+        } else {
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (n < N) v = *reinterpret_cast<const uint4*>(Wl + (int64_t)n * Kw + kk);
+            bv[j] = *reinterpret_cast<const bf16x8*>(&v);
+        }
+    }
+}
+
+// acc[i][j] = A[rows 16 i ..][0, K) x W[cols nc + 16 j ..][0, K)^T
+__device__ __forceinline__ void slice_product(const uint16_t* A, const uint16_t* Wl, int K, int Kw, int N, int nc,
+                                              bool short_rows, f32x4 (&acc)[8][4]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 bv[4], bn[4];
+    load_b_step(Wl, Kw, N, nc, 8 * (lane >> 4), short_rows, bv);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const int kk = k0 + 8 * (lane >> 4);
+        if (k0 + 32 < K) load_b_step(Wl, Kw, N, nc, kk + 32, short_rows, bn);
+        bf16x8 av[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) av[i] = *reinterpret_cast<const bf16x8*>(&A[(16 * i + (lane & 15)) * kFLd + kk]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = bn[j];
+    }
+}
+}  // namespace
+
+__global__ void __launch_bounds__(256, 2) forward_fused_kernel(FusedArgs a) {
+    __shared__ __align__(16) uint16_t act[kFT * kFLd];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t m0 = (int64_t)blockIdx.x * kFT;
     // input rows as BF16, K zero-padded to 32
     for (int e = tid; e < kFT * 32; e += 256) {
         const int r = e >> 5, k = e & 31;
         const int64_t m = m0 + r;
-        act[0][r * kFLd + k] = (m < a.batch && k < a.n_in) ? to_bf16(a.x[m * a.n_in + k]) : (uint16_t)0;
+        act[r * kFLd + k] = (m < a.batch && k < a.n_in) ? to_bf16(a.x[m * a.n_in + k]) : (uint16_t)0;
     }
     __syncthreads();
-    int cur = 0;
     for (int l = 0; l < a.layers; ++l) {
         const bool last = l + 1 == a.layers;
         const int K = l == 0 ? 32 : a.width;          // K of the stored operands (layer 0 padded)
         const int Kw = l == 0 ? a.n_in : a.width;     // row length of the weight matrix
-        const int N = last ? a.n_out : a.width;
         const uint16_t* Wl = a.W[l];
         const float* bl = a.bias[l];
-        const uint16_t* A = act[cur];
-        uint16_t* O = act[cur ^ 1];
-        for (int nc = 64 * w; nc < N; nc += 256) {
-            f32x4 acc[4][4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            for (int k0 = 0; k0 < K; k0 += 32) {
-                const int kk = k0 + 8 * (lane >> 4);
-                bf16x8 bv[4], av[4];
+        // hidden layers: one slice per wave (width <= 256); the last layer: as many as it needs
+        const int N = last ? a.n_out : a.width;
+        const int rounds = last ? (N + 255) / 256 : 1;
+        for (int t = 0; t < rounds; ++t) {
+            const int nc = 64 * w + 256 * t;
+            f32x4 acc[8][4];
+            if (nc < N) slice_product(act, Wl, K, Kw, N, nc, l == 0, acc);
+            if (!last) __syncthreads();   // every wave has read the layer input: overwrite it
+            if (nc < N) {
+                // lane holds D[4 (lane / 16) + q][lane % 16] of each block: rows
+                // 16 i + 4 (lane / 16) + q of this lane's column n
+                const int r0 = 4 * (lane >> 4);
+                const int64_t rows_left = a.batch - m0 - r0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int n = nc + 16 * j + (lane & 15);
-                    if (l == 0) {   // short rows (n_in < 8 possible): element by element
-                        uint16_t h[8];
+                    if (n >= N) continue;
+                    const float b = bl[n];
+                    if (last) {
+                        float* yb = a.y + (m0 + r0) * a.n_out + n;
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) h[i] = (n < N && kk + i < Kw) ? Wl[(int64_t)n * Kw + kk + i] : (uint16_t)0;
-                        bv[j] = *reinterpret_cast<const bf16x8*>(h);
+                        for (int i = 0; i < 8; ++i)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                if (16 * i + q < rows_left) yb[(int64_t)(16 * i + q) * a.n_out] = acc[i][j][q] + b;
                     } else {
-                        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                        if (n < N) v = *reinterpret_cast<const uint4*>(Wl + (int64_t)n * Kw + kk);
-                        bv[j] = *reinterpret_cast<const bf16x8*>(&v);
+                        uint16_t* ab = act + r0 * kFLd + n;
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) ab[(16 * i + q) * kFLd] = to_bf16(fmaxf(acc[i][j][q] + b, 0.0f));
                     }
                 }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    av[i] = *reinterpret_cast<const bf16x8*>(&A[(16 * i + (lane & 15)) * kFLd + kk]);
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
             }
-            // lane holds D[4 (lane / 16) + q][lane % 16] of each block
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int n = nc + 16 * j + (lane & 15);
-                if (n >= N) continue;
-                const float b = bl[n];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int r = 16 * i + 4 * (lane >> 4) + q;
-                        const float v = acc[i][j][q] + b;
-                        if (last) {
-                            if (m0 + r < a.batch) a.y[(m0 + r) * a.n_out + n] = v;
-                        } else {
-                            O[r * kFLd + n] = to_bf16(fmaxf(v, 0.0f));
-                        }
-                    }
-            }
+            if (!last) __syncthreads();
         }
-        __syncthreads();
-        cur ^= 1;
     }
 }
 
