@@ -270,7 +270,7 @@ def run_warmstart(args, B, torch):
         disc = W.large_argon_periodic(n_periodic=args.ws_particles)
         rows = [WS.evaluate_discharge(net, norm, disc, 0, args.ws_periods,
                                       log=lambda m: print(m, file=sys.stderr, flush=True),
-                                      max_seconds=args.ws_seconds)]
+                                      max_seconds=args.ws_seconds, continue_to=args.ws_continue)]
     else:
         params = W.surrogate_params(args.ws_n, 2)
         rows = WS.evaluate(net, norm, params, 2, args.ws_periods,
@@ -285,7 +285,8 @@ def run_warmstart(args, B, torch):
         config.update(cells=disc.n_cells, steps_per_rf_period=int(round(1.0 / (disc.rf_frequency_Hz * disc.dt_s))),
                       particles_per_species_initial=disc.n_super[0])
         if args.ws_target == "large":
-            config.update(particles_per_species_periodic=args.ws_particles, time_limit_s=args.ws_seconds)
+            config.update(particles_per_species_periodic=args.ws_particles, time_limit_s=args.ws_seconds,
+                          continue_to_period=args.ws_continue)
     if args.ws_out:
         with open(args.ws_out, "w") as f:
             json.dump(dict(summary=sm, rows=rows), f, indent=1)
@@ -370,7 +371,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="large", choices=sorted(workloads_by_name()) + ["warmstart", "mlp"])
     ap.add_argument("--ws-n", type=int, default=16, help="warmstart: held-out discharges")
     ap.add_argument("--ws-periods", type=int, default=1500, help="warmstart: RF period limit")
@@ -379,6 +380,9 @@ def main():
                     help="warmstart --ws-target large: particles per species in the periodic state")
     ap.add_argument("--ws-seconds", type=float, default=None,
                     help="warmstart --ws-target large: stop the runs after this many seconds")
+    ap.add_argument("--ws-continue", type=int, default=None,
+                    help="warmstart --ws-target large: keep both runs going to this period after they are "
+                         "steady, and compare their final windows there")
     ap.add_argument("--ws-target", default="heldout", choices=("heldout", "production", "large"),
                     help="warmstart: held-out draws of the training family, the production discharge, "
                          "or the large one")

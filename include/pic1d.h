@@ -178,8 +178,22 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out);
 
 /* Enqueue n_steps >= 0 PIC/MCC steps (Sec. 2.5) on the handle's stream and return
  * without waiting.  The collisions of the last step complete lazily at the next step or
- * at the next call that reads the state. */
+ * at the next call that reads the state.  With a graph size set (pic_set_graph), runs of
+ * that many steps are replayed from a captured HIP graph (captured on first use and again
+ * whenever the reordering phase or the pending state differs from the captured one); the
+ * rest, and every step while pic_timing is on, are launched one by one.  Results do not
+ * depend on which. */
 int pic_step(pic_handle* h, int64_t n_steps);
+
+/* Steps per captured graph for pic_step: 0 (the default) launches every step directly;
+ * an RF period (1 / (f dt) steps, Sec. 2.2) replays one graph per period.  Must be in
+ * [0, 100000] (PIC_EINVAL otherwise); waits for the stream and drops any captured graph.
+ * The graph is captured on a private stream of default priority and launched on the
+ * handle's stream; it holds kernel launches only.  pic_set_record_decisions drops it. */
+int pic_set_graph(pic_handle* h, int64_t steps_per_graph);
+
+/* Number of graph replays since the last pic_set_graph (for tests). */
+int pic_graph_launches(const pic_handle* h, int64_t* n);
 
 /* Wait for the handle's stream and report deferred device errors. */
 int pic_sync(pic_handle* h);

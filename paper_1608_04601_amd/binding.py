@@ -16,8 +16,8 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EHIP",
                 -5: "PIC_ENUMERIC", -6: "PIC_ESTATE"}
 MAX_PROCESSES = 16
 
-EXPORTED = ("pic_init", "pic_step", "pic_sync", "pic_moments", "pic_free", "pic_last_error",
-            "pic_get_counters", "pic_get_derived", "pic_get_particles", "pic_set_particles",
+EXPORTED = ("pic_init", "pic_step", "pic_set_graph", "pic_graph_launches", "pic_sync", "pic_moments", "pic_free",
+            "pic_last_error", "pic_get_counters", "pic_get_derived", "pic_get_particles", "pic_set_particles",
             "pic_get_fields", "pic_set_record_decisions", "pic_get_decisions", "pic_timing",
             "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
             "pic_batch_free", "pic_batch_last_error", "pic_batch_timing", "pic_batch_set_graph",
@@ -140,6 +140,8 @@ def load_library(path: str = None):
         "pic_batch_last_error": (C.c_char_p, [C.c_void_p]),
         "pic_batch_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "pic_batch_set_graph": (C.c_int, [C.c_void_p, C.c_int64]),
+        "pic_set_graph": (C.c_int, [C.c_void_p, C.c_int64]),
+        "pic_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
         "pic_batch_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
         "pic_batch_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
         "pic_batch_rebalance": (C.c_int, [C.c_void_p]),
@@ -496,6 +498,15 @@ class Discharge:
 
     def step(self, n):
         pic_step(self.h, n)
+
+    def set_graph(self, steps_per_graph):
+        """Replay runs of steps_per_graph steps from a captured HIP graph (0: launch each step)."""
+        _check(self.h, load_library().pic_set_graph(self.h, int(steps_per_graph)))
+
+    def graph_launches(self):
+        n = C.c_int64()
+        _check(self.h, load_library().pic_graph_launches(self.h, C.byref(n)))
+        return n.value
 
     def sync(self):
         pic_sync(self.h)

@@ -86,6 +86,14 @@ struct pic_handle {
     bool timing = false;
     std::vector<hipEvent_t> ev;
     int64_t n_timed = 0;
+    // captured graph of graph_steps steps (pic_set_graph), valid from reorder phase gsig and
+    // pending state gpend; it leaves the phase at gend
+    int64_t graph_steps = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap = nullptr;   // private stream the graph is captured on
+    int gsig = 0, gend = 0;
+    bool gpend = false;
+    int64_t graph_launches = 0;
 };
 
 namespace {
@@ -291,8 +299,20 @@ bool dev_alloc(pic_handle* h, T** out, size_t count) {
     return true;
 }
 
+void drop_graph(pic_handle* h) {
+    if (h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+}
+
 void release(pic_handle* h) {
     (void)hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    if (h->cap) {
+        (void)hipStreamDestroy(h->cap);
+        h->cap = nullptr;
+    }
     for (void* p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
@@ -580,21 +600,94 @@ fail_init:
     }
 }
 
+namespace {
+// One step: the particle pass (completing the previous step if it is pending), then the
+// periodic reordering when due.
+int solo_one_step(pic_handle* h) {
+    const int mode = pic::kAdvance | (h->pending ? pic::kComplete : 0);
+    if (launch_pass_timed(h, mode)) return h->status;
+    h->pending = true;
+    if (h->cfg.sort_every > 0 && ++h->since_sort >= h->cfg.sort_every) {
+        if (!hip_ok(h, pic::launch_sort(h->P, h->sort_cnt, h->sort_cursor, h->sort_blocks, h->sort_threads, h->stream),
+                    "sort launch"))
+            return h->status;
+        h->since_sort = 0;
+    }
+    return PIC_OK;
+}
+
+// Records graph_steps steps from the current reorder phase and pending state into a graph,
+// on a private stream.  Nothing runs; the host-side phase and pending flag are put back.
+int solo_capture(pic_handle* h) {
+    drop_graph(h);
+    if (!h->cap && !hip_ok(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "hipStreamCreateWithFlags"))
+        return h->status;
+    const int sig = h->since_sort;
+    const bool pend = h->pending;
+    const hipStream_t user = h->stream;
+    h->stream = h->cap;
+    hipGraph_t g = nullptr;
+    int rc = PIC_OK;
+    if (!hip_ok(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture")) {
+        rc = h->status;
+    } else {
+        for (int64_t k = 0; k < h->graph_steps && rc == PIC_OK; ++k) rc = solo_one_step(h);
+        const hipError_t e = hipStreamEndCapture(h->cap, &g);
+        if (rc == PIC_OK && !hip_ok(h, e, "hipStreamEndCapture")) rc = h->status;
+    }
+    h->gend = h->since_sort;
+    h->since_sort = sig;
+    h->pending = pend;
+    h->stream = user;
+    if (rc == PIC_OK && !hip_ok(h, hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0), "hipGraphInstantiate")) {
+        h->gexec = nullptr;
+        rc = h->status;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (rc == PIC_OK) {
+        h->gsig = sig;
+        h->gpend = pend;
+    }
+    return rc;
+}
+}  // namespace
+
 int pic_step(pic_handle* h, int64_t n_steps) {
     if (!h) return PIC_EINVAL;
     if (h->status) return h->status;
     if (n_steps < 0) return fail(h, PIC_EINVAL, "n_steps must be >= 0");
-    for (int64_t k = 0; k < n_steps; ++k) {
-        const int mode = pic::kAdvance | (h->pending ? pic::kComplete : 0);
-        if (launch_pass_timed(h, mode)) return h->status;
-        h->pending = true;
-        if (h->cfg.sort_every > 0 && ++h->since_sort >= h->cfg.sort_every) {
-            if (!hip_ok(h, pic::launch_sort(h->P, h->sort_cnt, h->sort_cursor, h->sort_blocks, h->sort_threads, h->stream),
-                        "sort launch"))
-                return h->status;
-            h->since_sort = 0;
+    int64_t k = 0;
+    while (k < n_steps) {
+        if (h->graph_steps > 0 && n_steps - k >= h->graph_steps && !h->timing) {
+            if ((!h->gexec || h->pending != h->gpend || h->since_sort != h->gsig) && solo_capture(h)) return h->status;
+            if (!hip_ok(h, hipGraphLaunch(h->gexec, h->stream), "hipGraphLaunch")) return h->status;
+            h->since_sort = h->gend;
+            h->pending = true;
+            ++h->graph_launches;
+            k += h->graph_steps;
+            continue;
         }
+        if (solo_one_step(h)) return h->status;
+        ++k;
     }
+    return PIC_OK;
+}
+
+int pic_set_graph(pic_handle* h, int64_t steps_per_graph) {
+    if (!h) return PIC_EINVAL;
+    if (h->status) return h->status;
+    if (steps_per_graph < 0 || steps_per_graph > 100000)
+        return fail(h, PIC_EINVAL, "steps_per_graph must be in [0, 100000]");
+    if (!hip_ok(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize")) return h->status;
+    drop_graph(h);
+    h->graph_steps = steps_per_graph;
+    h->graph_launches = 0;
+    return PIC_OK;
+}
+
+int pic_graph_launches(const pic_handle* h, int64_t* n) {
+    if (!h || !n) return PIC_EINVAL;
+    *n = h->graph_launches;
     return PIC_OK;
 }
 
@@ -1021,6 +1114,7 @@ int pic_set_record_decisions(pic_handle* h, int on) {
         }
         h->P.dec[s] = on ? h->dec_store[s] : nullptr;
     }
+    drop_graph(h);   // the captured launches carry the old parameters
     return PIC_OK;
 }
 

@@ -132,13 +132,16 @@ def period_profiles(view, disc):
     return np.array(prof)
 
 
-def run(discs, max_periods, warm=None, stream=None, log=None, max_seconds=None):
+def run(discs, max_periods, warm=None, stream=None, log=None, max_seconds=None, continue_to=None):
     """Advance the discharges (one batch) period by period; warm[k] (or None) holds the
     profiles (n_e, n_i, mean_energy_e, flux_i) that discharge k starts from.  Stops when
-    every discharge is steady, after max_periods, or once max_seconds have passed.  Returns
-    one dict per discharge: steady_at, periods, final (the last W-period mean profiles),
-    drift (the criterion's profile change between the last two windows), alive (electrons
-    and ions at the end), extinct."""
+    every discharge is steady, after max_periods, or once max_seconds have passed.  With
+    continue_to, every discharge keeps running (and recording its profiles) until that many
+    periods even after it became steady, so that the final windows show where the
+    discharges go after the criterion first held.  Returns one dict per discharge:
+    steady_at, periods, final (the last W-period mean profiles), drift (the criterion's
+    profile change between the last two windows), alive (electrons and ions at the end),
+    extinct."""
     spp = {int(round(1.0 / (d.rf_frequency_Hz * d.dt_s))) for d in discs}
     if len(spp) != 1:
         raise ValueError("all discharges of a run need the same steps per RF period")
@@ -163,7 +166,7 @@ def run(discs, max_periods, warm=None, stream=None, log=None, max_seconds=None):
             bt.step(spp)
             bt.sync()
             for k, d in enumerate(discs):
-                if det[k].done():
+                if det[k].done() and continue_to is None:
                     continue
                 cnt = bt[k].counters()
                 born, lost = cnt["births_total"], int(cnt["absorbed_total"][1].sum())
@@ -173,7 +176,7 @@ def run(discs, max_periods, warm=None, stream=None, log=None, max_seconds=None):
                 t_log = time.time()
                 n_done = sum(x.done() for x in det)
                 log(f"  period {c + 1}: {n_done}/{len(discs)} steady, {t_log - t0:.0f} s")
-            if all(x.done() for x in det):
+            if all(x.done() for x in det) and (continue_to is None or c + 1 >= continue_to):
                 break
             if max_seconds is not None and time.time() - t0 > max_seconds:
                 if log:
@@ -310,12 +313,13 @@ def evaluate(net, norm, params, seed, max_periods, log=None, index=None):
     return rows
 
 
-def evaluate_discharge(net, norm, disc, gas_id, max_periods, log=None, max_seconds=None):
+def evaluate_discharge(net, norm, disc, gas_id, max_periods, log=None, max_seconds=None, continue_to=None):
     """One discharge of any fidelity, cold and warm in one batch.  The network sees its
     (p, V0, d, gas id); the prediction is resampled onto the loader's points."""
     params = np.array([[disc.pressure_Pa, disc.rf_voltage_V, disc.gap_m, float(gas_id)]])
     pred = predict(net, norm, params)[0]
-    res = run([disc, disc], max_periods, warm=[None, warm_profiles(pred)], log=log, max_seconds=max_seconds)
+    res = run([disc, disc], max_periods, warm=[None, warm_profiles(pred)], log=log, max_seconds=max_seconds,
+              continue_to=continue_to)
     cold, hot = res
     return dict(params=[float(v) for v in params[0]], cold_steady_at=cold["steady_at"], warm_steady_at=hot["steady_at"],
                 extinct=bool(cold["extinct"] or hot["extinct"]), warm_vs_cold=profile_change(hot["final"], cold["final"]).tolist(),

@@ -140,7 +140,8 @@ def test_new_entry_points_reject_null_on_host():
     """Batches, warm start, diagnostics and current drive: NULL handles are rejected before
     any device work, and a negative current target is an invalid configuration."""
     L = B.load_library()
-    for f, args in ((L.pic_batch_set_graph, (None, 10)), (L.pic_batch_autotune, (None, 10, None)),
+    for f, args in ((L.pic_batch_set_graph, (None, 10)), (L.pic_set_graph, (None, 10)),
+                    (L.pic_batch_autotune, (None, 10, None)),
                     (L.pic_batch_rebalance, (None,)), (L.pic_batch_timing, (None, 1, None, None)),
                     (L.pic_batch_set_record_decisions, (None, 1)),
                     (L.pic_diag_config, (None, 10, 20.0)), (L.pic_diag_sample, (None,)),
@@ -149,6 +150,7 @@ def test_new_entry_points_reject_null_on_host():
         assert f(*args) == B.PIC_EINVAL, f.__name__
     n = C.c_int64()
     assert L.pic_batch_graph_launches(None, C.byref(n)) == B.PIC_EINVAL
+    assert L.pic_graph_launches(None, C.byref(n)) == B.PIC_EINVAL
     assert L.mlp_num_params(None, C.byref(n)) == B.PIC_EINVAL
 
 

@@ -216,3 +216,29 @@ def test_batch_member_single_step_parity_against_oracle():
             log(f"  step {c0['step']}->{c1['step']}: {n_cand} candidates, {len(o_par)} births, "
                 f"excused choices {len(unsure[0]) + len(unsure[1])}")
         assert v.counters()["numax_violations"] == (0, 0)
+
+
+def test_single_discharge_graph_replays_equal_eager_steps():
+    """One discharge stepped through pic_set_graph (graphs of 10 steps, reordering every 5)
+    against the same discharge launched step by step; eager steps, queries and
+    synchronisation between the replays, every replay checked; a run of 3 steps shifts the
+    reordering phase and forces a second capture, a change of decision recording a third."""
+    disc = _common_sort_members()[0]
+    with B.Discharge(disc) as g, B.Discharge(disc) as e:
+        g.set_graph(10)
+        replays = 0
+        for n in (10, 10, 3, 10, 10, 12):
+            g.step(n)
+            e.step(n)
+            replays += n // 10
+            g.sync()
+            e.sync()
+            assert g.graph_launches() == replays
+            _same(_state(g), _state(e), n)
+        B.pic_set_record_decisions(g.h, True)
+        B.pic_set_record_decisions(e.h, True)
+        g.step(10)
+        e.step(10)
+        assert g.graph_launches() == replays + 1
+        _same(_state(g), _state(e), "recording")
+        log(f"single-discharge graph replays checked: {replays + 1}")
