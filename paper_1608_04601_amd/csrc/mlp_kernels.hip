@@ -17,12 +17,14 @@ namespace mlp {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16, round to nearest even (NaN stays a quiet NaN).
-__device__ __forceinline__ uint16_t to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x0040u);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// FP32 -> BF16, round to nearest even (NaN stays a quiet NaN): one v_cvt_pk_bf16_f32.
+__device__ __forceinline__ uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// Two FP32 -> two BF16 in one 32-bit word (a in the low half), one v_cvt_pk_bf16_f32.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{a, b}), bf16x2));
 }
 
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -432,19 +434,23 @@ __device__ __forceinline__ void load_b_step(const uint16_t* Wl, int Kw, int N, i
     }
 }
 
-// acc[i][j] = A[rows 16 i ..][0, K) x W[cols nc + 16 j ..][0, K)^T
+// acc[i][j] = W[rows nc + 16 j ..][0, K) x A[rows 16 i ..][0, K)^T, the transposed block of
+// the layer's product (weights as the first MFMA operand, activations as the second), so a
+// lane ends with four consecutive outputs of one sample.  b0 holds the first K step's
+// weights, loaded by the caller; the next step's weights are in flight while a step
+// multiplies.
 __device__ __forceinline__ void slice_product(const uint16_t* A, const uint16_t* Wl, int K, int Kw, int N, int nc,
-                                              bool short_rows, f32x4 (&acc)[8][4]) {
+                                              bool short_rows, bf16x8 (&b0)[4], f32x4 (&acc)[8][4]) {
     const int lane = threadIdx.x & 63;
+    const int kl = 8 * (lane >> 4);
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    bf16x8 bv[4], bn[4];
-    load_b_step(Wl, Kw, N, nc, 8 * (lane >> 4), short_rows, bv);
     for (int k0 = 0; k0 < K; k0 += 32) {
-        const int kk = k0 + 8 * (lane >> 4);
-        if (k0 + 32 < K) load_b_step(Wl, Kw, N, nc, kk + 32, short_rows, bn);
+        const int kk = k0 + kl;
+        bf16x8 b1[4];
+        if (k0 + 32 < K) load_b_step(Wl, Kw, N, nc, kk + 32, short_rows, b1);
         bf16x8 av[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) av[i] = *reinterpret_cast<const bf16x8*>(&A[(16 * i + (lane & 15)) * kFLd + kk]);
@@ -452,9 +458,9 @@ __device__ __forceinline__ void slice_product(const uint16_t* A, const uint16_t*
         for (int i = 0; i < 8; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0[j], av[i], acc[i][j], 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = bn[j];
+        for (int j = 0; j < 4; ++j) b0[j] = b1[j];
     }
 }
 }  // namespace
@@ -463,50 +469,91 @@ __global__ void __launch_bounds__(256, 2) forward_fused_kernel(FusedArgs a) {
     __shared__ __align__(16) uint16_t act[kFT * kFLd];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t m0 = (int64_t)blockIdx.x * kFT;
-    // input rows as BF16, K zero-padded to 32
-    for (int e = tid; e < kFT * 32; e += 256) {
-        const int r = e >> 5, k = e & 31;
+    // input rows as BF16, K zero-padded to 32: every load issued before the first is used
+    constexpr int kInPerThread = kFT * 32 / 256;
+    float xin[kInPerThread];
+#pragma unroll
+    for (int u = 0; u < kInPerThread; ++u) {
+        const int e = tid + 256 * u, r = e >> 5, k = e & 31;
         const int64_t m = m0 + r;
-        act[r * kFLd + k] = (m < a.batch && k < a.n_in) ? to_bf16(a.x[m * a.n_in + k]) : (uint16_t)0;
+        xin[u] = (m < a.batch && k < a.n_in) ? a.x[m * a.n_in + k] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kInPerThread; ++u) {
+        const int e = tid + 256 * u;
+        act[(e >> 5) * kFLd + (e & 31)] = to_bf16(xin[u]);
     }
     __syncthreads();
+    // hidden layers: one slice per wave (width <= 256); the last layer: as many as it needs.
+    // The first K step of every slice is loaded while the slice before it finishes.
+    const int kl = 8 * (lane >> 4);
+    bf16x8 bfirst[4];
+    if (64 * w < a.width) load_b_step(a.W[0], a.n_in, a.width, 64 * w, kl, true, bfirst);
     for (int l = 0; l < a.layers; ++l) {
         const bool last = l + 1 == a.layers;
         const int K = l == 0 ? 32 : a.width;          // K of the stored operands (layer 0 padded)
         const int Kw = l == 0 ? a.n_in : a.width;     // row length of the weight matrix
         const uint16_t* Wl = a.W[l];
         const float* bl = a.bias[l];
-        // hidden layers: one slice per wave (width <= 256); the last layer: as many as it needs
         const int N = last ? a.n_out : a.width;
         const int rounds = last ? (N + 255) / 256 : 1;
         for (int t = 0; t < rounds; ++t) {
             const int nc = 64 * w + 256 * t;
+            // block (i, j): lane holds outputs nq + 16 j + q (q < 4) of sample 16 i + lane % 16
+            const int nq = nc + 4 * (lane >> 4);
             f32x4 acc[8][4];
-            if (nc < N) slice_product(act, Wl, K, Kw, N, nc, l == 0, acc);
+            float bias[4][4];   // loaded before the product, used after it
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bias[j][q] = nq + 16 * j + q < N ? bl[nq + 16 * j + q] : 0.0f;
+            if (nc < N) slice_product(act, Wl, K, Kw, N, nc, l == 0, bfirst, acc);
+            {   // the next slice's first K step: (l, t + 1), else (l + 1, 0)
+                const bool same = t + 1 < rounds;
+                const int l2 = same ? l : l + 1;
+                if (l2 < a.layers) {
+                    const int N2 = l2 + 1 == a.layers ? a.n_out : a.width;
+                    const int nc2 = same ? nc + 256 : 64 * w;
+                    if (nc2 < N2) load_b_step(a.W[l2], l2 == 0 ? a.n_in : a.width, N2, nc2, kl, l2 == 0, bfirst);
+                }
+            }
             if (!last) __syncthreads();   // every wave has read the layer input: overwrite it
             if (nc < N) {
-                // lane holds D[4 (lane / 16) + q][lane % 16] of each block: rows
-                // 16 i + 4 (lane / 16) + q of this lane's column n
-                const int r0 = 4 * (lane >> 4);
-                const int64_t rows_left = a.batch - m0 - r0;
+                const int ml = lane & 15;
+                if (!last) {   // N = width, a multiple of 32: a block's four outputs are all in range
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int n = nc + 16 * j + (lane & 15);
-                    if (n >= N) continue;
-                    const float b = bl[n];
-                    if (last) {
-                        float* yb = a.y + (m0 + r0) * a.n_out + n;
+                    for (int i = 0; i < 8; ++i)
 #pragma unroll
-                        for (int i = 0; i < 8; ++i)
+                        for (int j = 0; j < 4; ++j) {
+                            const int n0 = nq + 16 * j;
+                            if (n0 >= N) continue;
+                            uint2 pk;
+                            pk.x = pack_bf16(fmaxf(acc[i][j][0] + bias[j][0], 0.0f), fmaxf(acc[i][j][1] + bias[j][1], 0.0f));
+                            pk.y = pack_bf16(fmaxf(acc[i][j][2] + bias[j][2], 0.0f), fmaxf(acc[i][j][3] + bias[j][3], 0.0f));
+                            *reinterpret_cast<uint2*>(&act[(16 * i + ml) * kFLd + n0]) = pk;
+                        }
+                } else {
+                    // rows of four outputs 16-byte aligned
+                    const bool vec = (a.n_out & 3) == 0 && (reinterpret_cast<uintptr_t>(a.y) & 15) == 0;
 #pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                if (16 * i + q < rows_left) yb[(int64_t)(16 * i + q) * a.n_out] = acc[i][j][q] + b;
-                    } else {
-                        uint16_t* ab = act + r0 * kFLd + n;
+                    for (int i = 0; i < 8; ++i) {
+                        const int64_t m = m0 + 16 * i + ml;
+                        if (m >= a.batch) continue;
+                        float* yr = a.y + m * a.n_out;
 #pragma unroll
-                        for (int i = 0; i < 8; ++i)
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) ab[(16 * i + q) * kFLd] = to_bf16(fmaxf(acc[i][j][q] + b, 0.0f));
+                        for (int j = 0; j < 4; ++j) {
+                            const int n0 = nq + 16 * j;
+                            const float4 v = make_float4(acc[i][j][0] + bias[j][0], acc[i][j][1] + bias[j][1],
+                                                         acc[i][j][2] + bias[j][2], acc[i][j][3] + bias[j][3]);
+                            if (vec && n0 + 3 < N) {
+                                *reinterpret_cast<float4*>(yr + n0) = v;
+                            } else {
+                                if (n0 < N) yr[n0] = v.x;
+                                if (n0 + 1 < N) yr[n0 + 1] = v.y;
+                                if (n0 + 2 < N) yr[n0 + 2] = v.z;
+                                if (n0 + 3 < N) yr[n0 + 3] = v.w;
+                            }
+                        }
                     }
                 }
             }
