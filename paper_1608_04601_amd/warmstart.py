@@ -309,7 +309,8 @@ def evaluate(net, norm, params, seed, max_periods, log=None, index=None):
         rows.append(dict(params=[float(v) for v in params[k]], cold_steady_at=cold["steady_at"],
                          warm_steady_at=hot["steady_at"], extinct=bool(cold["extinct"] or hot["extinct"]),
                          warm_vs_cold=profile_change(hot["final"], cold["final"]).tolist(),
-                         prediction_vs_cold=profile_change(pred[k], cold["final"]).tolist()))
+                         prediction_vs_cold=profile_change(pred[k], cold["final"]).tolist(),
+                         periods_run=[cold["periods"], hot["periods"]]))
     return rows
 
 
@@ -333,8 +334,9 @@ def summarize(rows, max_periods):
     both = [r for r in ok if r["cold_steady_at"] is not None and r["warm_steady_at"] is not None]
     # a run that is not steady counts with the periods it ran (a lower bound: the period
     # limit, or fewer when a time limit stopped it)
-    cold = [r["cold_steady_at"] if r["cold_steady_at"] is not None else r["periods_run"][0] for r in ok]
-    warm = [r["warm_steady_at"] if r["warm_steady_at"] is not None else r["periods_run"][1] for r in ok]
+    ran = [r.get("periods_run", (max_periods, max_periods)) for r in ok]
+    cold = [r["cold_steady_at"] if r["cold_steady_at"] is not None else n[0] for r, n in zip(ok, ran)]
+    warm = [r["warm_steady_at"] if r["warm_steady_at"] is not None else n[1] for r, n in zip(ok, ran)]
     acc = [max(r["warm_vs_cold"]) for r in both]
     return dict(discharges=len(rows), extinct=len(rows) - len(ok), steady_both=len(both),
                 cold_periods_mean=float(np.mean(cold)) if cold else None,

@@ -119,3 +119,24 @@ def test_training_uses_only_steady_states():
     m = WS.training_mask(full)
     assert np.all(full["steady_at"][m] >= 0) and not np.any(full["extinct"][m])
     assert m.sum() < (~full["extinct"]).sum()   # some stored draws were still drifting
+
+
+def test_summary_counts_runs_that_are_not_steady():
+    """Runs that never met the criterion count with the periods they ran (the limit, or what
+    a time limit allowed); rows without that record count with the limit."""
+    def row(c, w, ran=None, extinct=False):
+        r = dict(cold_steady_at=c, warm_steady_at=w, extinct=extinct, warm_vs_cold=[0.01] * 5,
+                 prediction_vs_cold=[0.02] * 5)
+        if ran is not None:
+            r["periods_run"] = ran
+        return r
+    rows = [row(400, 100), row(None, 80, ran=(1500, 100)), row(None, None), row(300, None, ran=(320, 1500)),
+            row(200, 50, extinct=True)]
+    sm = WS.summarize(rows, 1500)
+    assert sm["discharges"] == 5 and sm["extinct"] == 1 and sm["steady_both"] == 1
+    assert sm["cold_periods_mean"] == (400 + 1500 + 1500 + 300) / 4
+    assert sm["warm_periods_mean"] == (100 + 80 + 1500 + 1500) / 4
+    assert sm["cold_not_steady"] == 2 and sm["warm_not_steady"] == 2
+    assert sm["warm_faster"] == 2   # a warm run that is not steady is never the faster one
+    big = WS.summarize([row(None, 212, ran=(1246, 232))], 6000)
+    assert big["cold_periods_mean"] == 1246 and big["warm_faster"] == 1
