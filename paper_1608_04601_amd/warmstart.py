@@ -44,8 +44,8 @@ from . import binding as B
 
 DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
 DATA_PATH = os.path.join(DATA_DIR, "steady_states_seed1.npz")
-# training draws: seeds 1, 3, 4, 5 and 6 (seed 2 is held out)
-DATA_PATHS = tuple(os.path.join(DATA_DIR, f"steady_states_seed{s}.npz") for s in (1, 3, 4, 5, 6))
+# training draws: seeds 1 and 3 to 9 (seed 2 is held out)
+DATA_PATHS = tuple(os.path.join(DATA_DIR, f"steady_states_seed{s}.npz") for s in (1, 3, 4, 5, 6, 7, 8, 9))
 N_POINTS = 128
 QUANTITIES = ("n_e", "n_i", "mean_energy_e", "phi", "flux_i")
 WIDTH, DEPTH = 256, 3
