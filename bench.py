@@ -245,7 +245,7 @@ def run_sweep(args, B, torch):
 def run_warmstart(args, B, torch):
     """RF periods to the periodic steady state, warm (surrogate) against cold (uniform)
     start: the network is trained on the GPU from stored steady states of the batched PIC
-    (parameter draws of seeds 1, 3, 4, 5 and 6), then held-out draws (seed 2) run cold and warm in one batch
+    (parameter draws of seeds 1 and 3 to 9), then held-out draws (seed 2) run cold and warm in one batch
     until the steady-state criterion holds (or the period limit)."""
     import numpy as np
 

@@ -1,6 +1,6 @@
 """What the trained surrogate gains over the plain method: the network is trained on the
 GPU (BF16 matrix cores) from the stored periodic states of the training draws (seeds 1,
-3, 4, 5 and 6) that the batched PIC produced, then two held-out seed-2 discharges run from a uniform start (the
+3 to 9) that the batched PIC produced, then two held-out seed-2 discharges run from a uniform start (the
 plain method) and from the predicted state, side by side in one batch.  Both must reach
 the steady-state criterion; the warm start in at most half the RF periods, and its final
 profiles within 3 % of the cold start's (the cold PIC run decides the error)."""
