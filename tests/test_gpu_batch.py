@@ -166,24 +166,22 @@ def _sweep_members():
     return [sw[3], checked, sw[7]]
 
 
-def test_batch_member_single_step_parity_against_oracle():
-    """A member of sweep shape (576 cells, 1.2e5 particles per species) advanced by batched
-    launches in the batch's own launch shape.  Its state is handed to the FP64 oracle and
-    both take one step: the drift, deposit and solve run in the batched advancing launch, the
-    MCC and births in the batched completing launch, with decision records on.  Checked as
-    in the single-discharge protocol: fields, per-id positions and velocities, candidate
-    sets, process choices outside the margin band, ionisation-product ids."""
+def _member_parity(discs, k, checkpoints):
+    """Advance the batch by batched launches; at each checkpoint hand member k's state to the
+    FP64 oracle and take one step on both: the drift, deposit and solve in the batched
+    advancing launch, the MCC and births in the batched completing launch, with decision
+    records on.  Checked as in the single-discharge protocol: fields, per-id positions and
+    velocities, candidate sets, process choices outside the margin band,
+    ionisation-product ids."""
     from gpu_common import REL_FIELD, compare_decisions, compare_species, oracle_input
     from oracle import Oracle
-    discs = _sweep_members()
-    k = 1
     disc = discs[k]
     with B.Batch(discs) as bt:
-        log(f"batch member parity: {disc.n_cells} cells, {disc.n_super[0]} per species, "
-            f"batch blocks {[bt.blocks(q) for q in range(len(bt))]}")
+        log(f"batch member parity: member {k} of {len(discs)}, {disc.n_cells} cells, {disc.n_super[0]} per species, "
+            f"{bt.blocks(k)} of {sum(bt.blocks(q) for q in range(len(bt)))} workgroups")
         bt.record_decisions(True)
-        for done in (0, 60):
-            bt.step(60)
+        for n in checkpoints:
+            bt.step(n)
             bt.sync()                  # batched completing launch: nothing is left pending
             v = bt[k]
             c0 = v.counters()
@@ -216,6 +214,23 @@ def test_batch_member_single_step_parity_against_oracle():
             log(f"  step {c0['step']}->{c1['step']}: {n_cand} candidates, {len(o_par)} births, "
                 f"excused choices {len(unsure[0]) + len(unsure[1])}")
         assert v.counters()["numax_violations"] == (0, 0)
+
+
+def test_batch_member_single_step_parity_against_oracle():
+    """A member of sweep shape (576 cells, 1.2e5 particles per species) advanced by batched
+    launches in the batch's own launch shape, checked against the oracle after 60 and 121
+    steps."""
+    _member_parity(_sweep_members(), 1, (60, 60))
+
+
+def test_full_sweep_member_single_step_parity_against_oracle():
+    """The full 64-discharge sweep in the launch shape its benchmark times (the batch's
+    default schedule, which its tuner keeps), one member checked against the oracle after 45
+    steps, when the uniform starts are ionising hardest; the member with the most particles
+    is the one checked."""
+    discs = W.sweep_argon()
+    k = int(np.argmax([d.n_super[0] for d in discs]))
+    _member_parity(discs, k, (45,))
 
 
 def test_single_discharge_graph_replays_equal_eager_steps():
