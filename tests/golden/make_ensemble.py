@@ -1,8 +1,11 @@
-"""Write tests/golden/argon_small_ensemble.json: window moments of the FP64 oracle for the
-small argon-like discharge (2 cm, 128 cells, 100 V, 20 Pa, 2e4 + 2e4 particles,
-dt = T_rf/400), seeds 0..7, averaged over RF cycles 10..20 after a cold start.
+"""Write the statistical-parity golden files from the FP64 oracle: window moments averaged
+over RF cycles 10..20 after a cold start, seeds 0..7, for
+* argon_small_ensemble.json: the small argon-like discharge (2 cm, 128 cells, 100 V, 20 Pa,
+  2e4 + 2e4 particles, dt = T_rf/400);
+* helium_small_ensemble.json: the small helium-like discharge (2.5 cm, 128 cells, 200 V,
+  40 Pa, 2e4 + 2e4 particles, dt = T_rf/800).
 
-Calls only oracle/ and workloads/.  Run:  python tests/golden/make_ensemble.py
+Calls only oracle/ and workloads/.  Run:  python tests/golden/make_ensemble.py [argon|helium]
 """
 import json
 import os
@@ -19,13 +22,18 @@ CYCLES_SKIP, CYCLES_TOTAL = 10, 20
 KEYS = ("n_e", "n_i", "mean_energy_e", "flux_i", "phi")
 
 
-def run(seed):
+CASES = {"argon": ("small_argon", "argon_small_ensemble.json"),
+         "helium": ("small_helium", "helium_small_ensemble.json")}
+
+
+def run(args):
+    case, seed = args
     os.environ["OMP_NUM_THREADS"] = "1"
     import numpy as np
 
     import workloads as W
     from oracle import Oracle
-    disc = W.small_argon(seed=seed)
+    disc = getattr(W, CASES[case][0])(seed=seed)
     spp = disc.steps_per_period
     o = Oracle(disc)
     t0 = time.time()
@@ -43,13 +51,14 @@ def run(seed):
 
 
 def main():
+    case = sys.argv[1] if len(sys.argv) > 1 else "argon"
     with Pool(min(8, len(SEEDS))) as p:
-        res = p.map(run, SEEDS)
+        res = p.map(run, [(case, s) for s in SEEDS])
     import workloads as W
-    disc = W.small_argon()
+    disc = getattr(W, CASES[case][0])()
     doc = {"workload": disc.name, "seeds": SEEDS, "cycles": [CYCLES_SKIP, CYCLES_TOTAL],
            "steps_per_period": disc.steps_per_period, "runs": res}
-    with open(os.path.join(HERE, "argon_small_ensemble.json"), "w") as f:
+    with open(os.path.join(HERE, CASES[case][1]), "w") as f:
         json.dump(doc, f, separators=(",", ":"))
     for r in res:
         print(r["seed"], r["alive"], r["next_id"], f"J0={r['J0']:.3f}", f"{r['seconds']:.0f}s")

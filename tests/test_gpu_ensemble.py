@@ -1,5 +1,7 @@
 """Statistical parity: cycle-averaged profiles of the GPU path against the FP64 oracle's
-ensemble (small argon-like discharge, RF cycles 10..20 of a cold start).
+ensemble, RF cycles 10..20 of a cold start, for two discharges: the small argon-like one
+(128 cells, T_rf/400) and the small helium-like one (128 cells, T_rf/800; ion table in the
+centre-of-mass frame, backward ion scattering).
 
 The oracle's runs (seeds 0..7) come from tests/golden/make_ensemble.py (oracle only).  The
 GPU runs use seeds 100..115, disjoint from those: the two ensembles share no initial load
@@ -21,7 +23,9 @@ from paper_1608_04601_amd import binding as B
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "argon_small_ensemble.json")
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+CASES = {"argon": (W.small_argon, "argon_small_ensemble.json"),
+         "helium": (W.small_helium, "helium_small_ensemble.json")}
 KEYS = ("n_e", "n_i", "mean_energy_e", "flux_i", "phi")
 GPU_SEEDS = tuple(range(100, 116))
 
@@ -30,18 +34,22 @@ def _arr(v):
     return np.array([np.nan if x is None else x for x in v], dtype=float)
 
 
-@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle ensemble not generated")
-def test_cycle_averaged_profiles_match_oracle_ensemble():
-    doc = json.load(open(GOLDEN))
+@pytest.mark.parametrize("case", list(CASES))
+def test_cycle_averaged_profiles_match_oracle_ensemble(case):
+    make, name = CASES[case]
+    path = os.path.join(GOLDEN_DIR, name)
+    if not os.path.exists(path):
+        pytest.skip(f"oracle ensemble {name} not generated")
+    doc = json.load(open(path))
     c0, c1 = doc["cycles"]
     orc = {k: np.stack([_arr(r[k]) for r in doc["runs"]]) for k in KEYS}
     gpu = {k: [] for k in KEYS}
     scal = {"J0": [], "flux_i_powered": []}
     assert not set(GPU_SEEDS) & set(doc["seeds"])
     for seed in GPU_SEEDS:
-        disc = W.small_argon(seed=seed)
+        disc = make(seed=seed)
         spp = disc.steps_per_period
-        log(f"ensemble seed {seed}")
+        log(f"ensemble {case} seed {seed}")
         with B.Discharge(disc) as d:
             d.step(c0 * spp)
             d.moments(reset=True)

@@ -148,6 +148,20 @@ def small_argon(seed: int = 0, n_super: int = 20_000) -> Discharge:
         processes=argon_like(top, top), sort_every=20, moments_every=1)
 
 
+def small_helium(seed: int = 0, n_super: int = 20_000) -> Discharge:
+    """Plain FP64-checkable helium discharge (the second statistical parity case):
+    helium-like, 2.5 cm, 128 cells, 200 V, 40 Pa, 300 K, 2e4 particles per species,
+    n_init 1e15 m^-3, 2 eV / 0.026 eV, dt = T_rf/800 (ion table in the centre-of-mass
+    frame, backward ion scattering)."""
+    top = _table_top(200.0)
+    return Discharge(
+        name="helium_2.5cm_128c_40Pa_200V", gap_m=0.025, pressure_Pa=40.0, gas_temperature_K=300.0,
+        gas_mass_amu=AMU_HE, rf_voltage_V=200.0, rf_frequency_Hz=F_RF, dt_s=1.0 / (F_RF * 800),
+        n_cells=128, n_init_m3=1e15, te_init_eV=2.0, ti_init_eV=0.026,
+        n_super=(n_super, n_super), capacity=(4 * n_super, 4 * n_super), seed=seed,
+        processes=helium_like(top, top), sort_every=20, moments_every=1)
+
+
 def production_helium(seed: int = 0, n_super: int = 1_000_000) -> Discharge:
     """Single discharge at production size: helium-like, 2.5 cm, 512 cells, 200 V, 40 Pa,
     1e6 particles per species, dt = T_rf/2000."""
