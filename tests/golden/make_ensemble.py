@@ -1,11 +1,14 @@
 """Write the statistical-parity golden files from the FP64 oracle: window moments averaged
-over RF cycles 10..20 after a cold start, seeds 0..7, for
+over RF cycles after a cold start, seeds 0..7, for
 * argon_small_ensemble.json: the small argon-like discharge (2 cm, 128 cells, 100 V, 20 Pa,
-  2e4 + 2e4 particles, dt = T_rf/400);
+  2e4 + 2e4 particles, dt = T_rf/400), cycles 10..20;
 * helium_small_ensemble.json: the small helium-like discharge (2.5 cm, 128 cells, 200 V,
-  40 Pa, 2e4 + 2e4 particles, dt = T_rf/800).
+  40 Pa, 2e4 + 2e4 particles, dt = T_rf/800), cycles 10..20;
+* argon_4096c_ensemble.json: the large argon-like discharge's geometry (3 cm, 4096 cells,
+  300 V, 80 Pa, dt = T_rf/4000) with 5e4 + 5e4 particles at the start, cycles 4..8.
 
-Calls only oracle/ and workloads/.  Run:  python tests/golden/make_ensemble.py [argon|helium]
+Calls only oracle/ and workloads/.
+Run:  python tests/golden/make_ensemble.py [argon|helium|large]
 """
 import json
 import os
@@ -18,12 +21,12 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 SEEDS = list(range(8))
-CYCLES_SKIP, CYCLES_TOTAL = 10, 20
 KEYS = ("n_e", "n_i", "mean_energy_e", "flux_i", "phi")
 
-
-CASES = {"argon": ("small_argon", "argon_small_ensemble.json"),
-         "helium": ("small_helium", "helium_small_ensemble.json")}
+# workload, its arguments, output file, (cycles skipped, cycles total)
+CASES = {"argon": ("small_argon", {}, "argon_small_ensemble.json", (10, 20)),
+         "helium": ("small_helium", {}, "helium_small_ensemble.json", (10, 20)),
+         "large": ("large_argon", {"n_super": 50_000}, "argon_4096c_ensemble.json", (4, 8))}
 
 
 def run(args):
@@ -33,14 +36,15 @@ def run(args):
 
     import workloads as W
     from oracle import Oracle
-    disc = getattr(W, CASES[case][0])(seed=seed)
+    name, kw, _, (skip, total) = CASES[case]
+    disc = getattr(W, name)(seed=seed, **kw)
     spp = disc.steps_per_period
     o = Oracle(disc)
     t0 = time.time()
-    for _ in range(CYCLES_SKIP * spp):
+    for _ in range(skip * spp):
         o.step()
     o.reset_moments()
-    for _ in range((CYCLES_TOTAL - CYCLES_SKIP) * spp):
+    for _ in range((total - skip) * spp):
         o.step()
     m = o.moments()
     out = {k: [float(v) if np.isfinite(v) else None for v in m[k]] for k in KEYS}
@@ -55,10 +59,11 @@ def main():
     with Pool(min(8, len(SEEDS))) as p:
         res = p.map(run, [(case, s) for s in SEEDS])
     import workloads as W
-    disc = getattr(W, CASES[case][0])()
-    doc = {"workload": disc.name, "seeds": SEEDS, "cycles": [CYCLES_SKIP, CYCLES_TOTAL],
+    name, kw, out, (skip, total) = CASES[case]
+    disc = getattr(W, name)(**kw)
+    doc = {"workload": disc.name, "seeds": SEEDS, "cycles": [skip, total],
            "steps_per_period": disc.steps_per_period, "runs": res}
-    with open(os.path.join(HERE, CASES[case][1]), "w") as f:
+    with open(os.path.join(HERE, out), "w") as f:
         json.dump(doc, f, separators=(",", ":"))
     for r in res:
         print(r["seed"], r["alive"], r["next_id"], f"J0={r['J0']:.3f}", f"{r['seconds']:.0f}s")

@@ -1,21 +1,32 @@
 """Statistical parity: cycle-averaged profiles of the GPU path against the FP64 oracle's
-ensemble, RF cycles 10..20 of a cold start, for two discharges: the small argon-like one
-(128 cells, T_rf/400) and the small helium-like one (128 cells, T_rf/800; ion table in the
-centre-of-mass frame, backward ion scattering).
+ensemble, after a cold start, for three discharges: the small argon-like one (128 cells,
+T_rf/400, cycles 10..20), the small helium-like one (128 cells, T_rf/800, cycles 10..20; ion
+table in the centre-of-mass frame, backward ion scattering) and the large argon-like one's
+geometry and time step (4096 cells, T_rf/4000, reordering every 50 steps, cycles 4..8) with
+5e4 particles per species at the start.
 
 The oracle's runs (seeds 0..7) come from tests/golden/make_ensemble.py (oracle only).  The
 GPU runs use seeds 100..115, disjoint from those: the two ensembles share no initial load
 and no collision draw (the draws are keyed by seed, id and step), so they are independent
-samples of the same process, as the 2-sigma rule assumes.  At every node
-|mu_gpu - mu_oracle| <= max(0.03 max|mu_oracle|, 2 sqrt(s_gpu^2/n_gpu + s_oracle^2/n_oracle));
+samples of the same process.  At every compared point
+|mu_gpu - mu_oracle| <= max(0.03 max|mu_oracle|, c sqrt(s_gpu^2/n_gpu + s_oracle^2/n_oracle));
 the mean electron energy is compared only where n_e >= 1e-3 max n_e (it is undefined in the
 sheaths).
+
+The two 128-cell discharges are compared node by node with c = 2.  The 4096-cell one has
+about 12 particles per cell at the start, so its node profiles are mostly noise: it is
+compared on 128 blocks of 32 nodes (the resolution of the other two), and, since 128 blocks
+per quantity are tested with spreads estimated from 8 and 16 runs, c is the two-sided
+Student-t quantile at family-wise level 0.05 (Bonferroni over the blocks) for each block's
+Welch-Satterthwaite degrees of freedom (c = 4.2..5.8 here).  Where the profiles carry
+signal the 3 % term is the binding one in all three cases.
 """
 import json
 import os
 
 import numpy as np
 import pytest
+from scipy import stats
 
 import workloads as W
 from gpu_common import log
@@ -24,8 +35,13 @@ from paper_1608_04601_amd import binding as B
 pytestmark = pytest.mark.gpu
 
 GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-CASES = {"argon": (W.small_argon, "argon_small_ensemble.json"),
-         "helium": (W.small_helium, "helium_small_ensemble.json")}
+# case -> (discharge for a seed, oracle ensemble file, nodes per compared block)
+CASES = {"argon": (W.small_argon, "argon_small_ensemble.json", 1),
+         "helium": (W.small_helium, "helium_small_ensemble.json", 1),
+         # the uniform start ionises: storage for 8x the initial count (storage does not change results)
+         "large": (lambda seed: W.large_argon(seed=seed, n_super=50_000).replace(capacity=(400_000, 400_000)),
+                   "argon_4096c_ensemble.json", 32)}
+FAMILY_ALPHA = 0.05
 KEYS = ("n_e", "n_i", "mean_energy_e", "flux_i", "phi")
 GPU_SEEDS = tuple(range(100, 116))
 
@@ -34,9 +50,27 @@ def _arr(v):
     return np.array([np.nan if x is None else x for x in v], dtype=float)
 
 
+def _blocks(runs, width):
+    """Per-run means over consecutive blocks of `width` nodes (the last node joins the last
+    block); NaN nodes are left out of a block's mean."""
+    if width == 1:
+        return runs
+    idx = np.array_split(np.arange(runs.shape[1]), runs.shape[1] // width)
+    return np.stack([np.nanmean(runs[:, b], 1) for b in idx], 1)
+
+
+def _band_factor(var_g, var_o, ng, no, width):
+    """2 for node-by-node comparison; else the Bonferroni-corrected two-sided t quantile
+    for the Welch-Satterthwaite degrees of freedom of each block."""
+    if width == 1:
+        return 2.0
+    nu = (var_g + var_o) ** 2 / (var_g ** 2 / (ng - 1) + var_o ** 2 / (no - 1))
+    return stats.t.ppf(1.0 - FAMILY_ALPHA / (2 * var_g.size), nu)
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_cycle_averaged_profiles_match_oracle_ensemble(case):
-    make, name = CASES[case]
+    make, name, width = CASES[case]
     path = os.path.join(GOLDEN_DIR, name)
     if not os.path.exists(path):
         pytest.skip(f"oracle ensemble {name} not generated")
@@ -63,14 +97,23 @@ def test_cycle_averaged_profiles_match_oracle_ensemble(case):
         scal["flux_i_powered"].append(m["flux_i_powered"])
     gpu = {k: np.stack(v) for k, v in gpu.items()}
     ng, no = len(GPU_SEEDS), len(doc["seeds"])
-    ne_mask = np.nanmean(orc["n_e"], 0) >= 1e-3 * np.nanmax(np.nanmean(orc["n_e"], 0))
+    ne = np.nanmean(orc["n_e"], 0)
+    ne_mask = ne >= 1e-3 * np.nanmax(ne)
     for k in KEYS:
-        mg, mo = np.nanmean(gpu[k], 0), np.nanmean(orc[k], 0)
-        sg, so = np.nanstd(gpu[k], 0, ddof=1), np.nanstd(orc[k], 0, ddof=1)
-        tol = np.maximum(0.03 * np.nanmax(np.abs(mo)), 2 * np.sqrt(sg ** 2 / ng + so ** 2 / no))
-        sel = ne_mask if k == "mean_energy_e" else np.ones_like(mo, bool)
-        bad = (np.abs(mg - mo) > tol) & sel
-        log(f"  {k}: max |dmu|/tol = {np.nanmax(np.abs(mg - mo)[sel] / tol[sel]):.3f}")
+        g, o = gpu[k].astype(float), orc[k].copy()
+        floor = 0.03 * np.nanmax(np.abs(np.nanmean(_blocks(o, width), 0)))
+        if k == "mean_energy_e":
+            g[:, ~ne_mask] = np.nan
+            o[:, ~ne_mask] = np.nan
+        g, o = _blocks(g, width), _blocks(o, width)
+        sel = ~np.isnan(np.nanmean(o, 0))
+        g, o = g[:, sel], o[:, sel]
+        mg, mo = np.nanmean(g, 0), np.nanmean(o, 0)
+        vg, vo = np.nanvar(g, 0, ddof=1) / ng, np.nanvar(o, 0, ddof=1) / no
+        c = _band_factor(vg, vo, ng, no, width)
+        tol = np.maximum(floor, c * np.sqrt(vg + vo))
+        bad = np.abs(mg - mo) > tol
+        log(f"  {k}: max |dmu|/tol = {np.nanmax(np.abs(mg - mo) / tol):.3f} over {mo.size} points")
         assert not bad.any(), (k, np.nonzero(bad)[0][:10])
     for k, vals in scal.items():
         mo = np.array([r[k] for r in doc["runs"]])
