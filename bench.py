@@ -457,7 +457,9 @@ def main():
         min_bytes = sum(b * 0.5 * (c2["n_alive"][s] + c3["n_alive"][s])
                         for s, b in enumerate((MIN_BYTES_ELECTRON_STEP, MIN_BYTES_ION_STEP)))
         achieved_min = min_bytes / (kern_ms * 1e-3) / 1e9
-        bpps = stored_traffic(args.workload)
+        _, _, dynamic = d.launch_shape()
+        kernel = "pass_dyn_kernel" if dynamic else "pass_kernel"
+        bpps = stored_traffic(args.workload, kernel)
         traffic = None if bpps is None else bpps * units   # bytes per launch at this launch's size
     finally:
         d.close()
@@ -509,7 +511,7 @@ def main():
             "frac_traffic": None if traffic is None else traffic / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "copy_GBs": copy_gbs,
             "frac_of_copy": achieved / copy_gbs,
-            "kernel": "pass_kernel (fused complete+advance)",
+            "kernel": kernel + " (fused complete+advance" + (", dynamic work distribution)" if dynamic else ")"),
             "kernel_ms_mean": kern_ms,
             "launches_timed": n_launch,
             "achieved_min_bytes": achieved_min,

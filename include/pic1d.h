@@ -195,6 +195,13 @@ int pic_set_graph(pic_handle* h, int64_t steps_per_graph);
 /* Number of graph replays since the last pic_set_graph (for tests). */
 int pic_graph_launches(const pic_handle* h, int64_t* n);
 
+/* Launch shape of the particle pass, fixed at pic_init: workgroups, threads per workgroup,
+ * and dynamic = 1 when the pass takes its slots in blocks from a per-species counter as
+ * workgroups become free (chosen when every workgroup starts with at least 65536 slots;
+ * otherwise 0: each workgroup has a fixed contiguous slot range).  Results do not depend on
+ * it.  Any output pointer may be NULL; PIC_EINVAL if h is NULL. */
+int pic_launch_shape(const pic_handle* h, int* blocks, int* threads, int* dynamic);
+
 /* Wait for the handle's stream and report deferred device errors. */
 int pic_sync(pic_handle* h);
 

@@ -16,7 +16,7 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EHIP",
                 -5: "PIC_ENUMERIC", -6: "PIC_ESTATE"}
 MAX_PROCESSES = 16
 
-EXPORTED = ("pic_init", "pic_step", "pic_set_graph", "pic_graph_launches", "pic_sync", "pic_moments", "pic_free",
+EXPORTED = ("pic_init", "pic_step", "pic_set_graph", "pic_graph_launches", "pic_launch_shape", "pic_sync", "pic_moments", "pic_free",
             "pic_last_error", "pic_get_counters", "pic_get_derived", "pic_get_particles", "pic_set_particles",
             "pic_get_fields", "pic_set_record_decisions", "pic_get_decisions", "pic_timing",
             "pic_batch_init", "pic_batch_step", "pic_batch_sync", "pic_batch_handle", "pic_batch_blocks",
@@ -142,6 +142,7 @@ def load_library(path: str = None):
         "pic_batch_set_graph": (C.c_int, [C.c_void_p, C.c_int64]),
         "pic_set_graph": (C.c_int, [C.c_void_p, C.c_int64]),
         "pic_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+        "pic_launch_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "pic_batch_graph_launches": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
         "pic_batch_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
         "pic_batch_rebalance": (C.c_int, [C.c_void_p]),
@@ -507,6 +508,12 @@ class Discharge:
         n = C.c_int64()
         _check(self.h, load_library().pic_graph_launches(self.h, C.byref(n)))
         return n.value
+
+    def launch_shape(self):
+        """(workgroups, threads per workgroup, dynamic work distribution) of the particle pass."""
+        g, t, d = C.c_int(), C.c_int(), C.c_int()
+        _check(self.h, load_library().pic_launch_shape(self.h, C.byref(g), C.byref(t), C.byref(d)))
+        return g.value, t.value, bool(d.value)
 
     def sync(self):
         pic_sync(self.h)

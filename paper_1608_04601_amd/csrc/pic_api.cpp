@@ -15,7 +15,7 @@
 #include "pic_types.hpp"
 
 namespace pic {
-hipError_t launch_pass(int mode, const Params& P, int blocks, int threads, size_t lds, hipStream_t st);
+hipError_t launch_pass(int mode, const Params& P, int blocks, int threads, size_t lds, hipStream_t st, bool dyn);
 hipError_t launch_load(const Params& P, int s, int64_t n, double vth, hipStream_t st);
 hipError_t launch_sort(const Params& P, unsigned* cnt, unsigned* cursor, int blocks, int threads, hipStream_t st);
 hipError_t launch_load_profile(const Params& P, int s, int64_t n, unsigned b, const double* tab, int np, double h_m,
@@ -74,6 +74,7 @@ struct pic_handle {
     int diag_capacity_bins = 0;
     double diag_umax = 0.0;
     int blocks = 1, threads = 256;
+    bool dyn_pass = false;   // the pass with the dynamic work distribution (pass_dyn_kernel)
     size_t lds = 0;
     int sort_blocks = 1, sort_threads = 256;
     // sequencing
@@ -122,7 +123,7 @@ bool hip_ok(pic_handle* h, hipError_t e, const char* what) {
 // epilogue layout (control block copy, three FP64 node arrays, scratch, then the
 // potential or, before the solve, the birth keys and parents).
 size_t pass_lds_bytes(int nn, int nt) {
-    const size_t pass_lds = 32 * 4 + (size_t)nn * (8 + 8 + 4) + (size_t)(pic::kNullBins + 1) * 4 +
+    const size_t pass_lds = 32 * 4 + pic::kPassRingBytes + (size_t)nn * (8 + 8 + 4) + (size_t)(pic::kNullBins + 1) * 4 +
                             (size_t)(nt / 64) * 128 * 7 * 4;
     const size_t epi_lds = 512 + (size_t)24 * nn + 512 + std::max((size_t)8 * nn, (size_t)pic::kBirthSortCap * 8);
     return std::max(pass_lds, epi_lds);
@@ -332,6 +333,7 @@ int check_device(pic_handle* h) {
         return fail(h, PIC_ECAPACITY, what);
     }
     if (err & pic::kErrNumeric) return fail(h, PIC_ENUMERIC, "non-finite particle coordinate");
+    if (err & pic::kErrSchedule) return fail(h, PIC_EHIP, "particle pass: work distribution wait exceeded its bound");
     return PIC_OK;
 }
 
@@ -358,7 +360,7 @@ int launch_pass_timed(pic_handle* h, int mode) {
         }
     }
     const int launch_mode = mode | ((h->P.dec[0] && (mode & pic::kComplete)) ? pic::kRecord : 0);
-    if (!hip_ok(h, pic::launch_pass(launch_mode, h->P, h->blocks, h->threads, h->lds, h->stream),
+    if (!hip_ok(h, pic::launch_pass(launch_mode, h->P, h->blocks, h->threads, h->lds, h->stream, h->dyn_pass),
                 "pass_kernel launch"))
         return h->status;
     if (t && h->timing) {
@@ -552,6 +554,9 @@ int pic_init(const pic_config* cfg, void* hip_stream, pic_handle** out) {
             const int64_t want = std::max<int64_t>(1, (total + per_block - 1) / per_block);
             h->blocks = (int)std::min(want, resident);
         }
+        // Large shares per workgroup: the dynamic work distribution keeps the workgroups
+        // together (smaller ones keep the static cut, which was faster there).
+        h->dyn_pass = h->blocks > 1 && total / h->blocks >= 2 * pic::kPassDynMinShare;
 
         if (!hip_ok(h, hipMemcpyAsync(tab, htab.data(), htab.size() * sizeof(float), hipMemcpyHostToDevice, h->stream),
                     "upload tables") ||
@@ -688,6 +693,14 @@ int pic_set_graph(pic_handle* h, int64_t steps_per_graph) {
 int pic_graph_launches(const pic_handle* h, int64_t* n) {
     if (!h || !n) return PIC_EINVAL;
     *n = h->graph_launches;
+    return PIC_OK;
+}
+
+int pic_launch_shape(const pic_handle* h, int* blocks, int* threads, int* dynamic) {
+    if (!h) return PIC_EINVAL;
+    if (blocks) *blocks = h->blocks;
+    if (threads) *threads = h->threads;
+    if (dynamic) *dynamic = h->dyn_pass ? 1 : 0;
     return PIC_OK;
 }
 
@@ -928,7 +941,7 @@ int load_from_tables(pic_handle* h, pic::Ctrl& c, int32_t n_points, const double
     if (!hip_ok(h, hipMemcpyAsync(h->P.ctrl, &c, sizeof(c), hipMemcpyHostToDevice, h->stream), "write ctrl") ||
         !hip_ok(h, hipMemsetAsync(h->P.Qs, 0, 2 * (h->cfg.n_cells + 1) * sizeof(unsigned long long), h->stream),
                 "zero Q") ||
-        !hip_ok(h, pic::launch_pass(pic::kDeposit, h->P, h->blocks, h->threads, h->lds, h->stream),
+        !hip_ok(h, pic::launch_pass(pic::kDeposit, h->P, h->blocks, h->threads, h->lds, h->stream, h->dyn_pass),
                 "deposit pass"))
         return h->status;
     return check_device(h);

@@ -146,6 +146,10 @@ struct Lds {
     uint32_t* qid;
     float* qvy;              // electrons only
     float* qvz;
+    // work distribution: block ids of the workgroup's j-th block, tagged (j << 32 | id), and
+    // the count of sub-blocks handed to its waves
+    unsigned long long* ring;   // kPassRing
+    uint32_t* sub;
 };
 
 // After the drift of an ionisation product: absorb at the electrodes (Sec. 2.5, ties
@@ -691,6 +695,155 @@ __device__ __forceinline__ void run_range(const Params& P, const Lds& L, int64_t
     if ((MODE & kComplete) && nq > 0u) drain_queue<MODE, S>(P, L, wq, nq, nq, stepf, cur, ns0, ns1, sample);
 }
 
+// Dynamic work distribution (pass_dyn_kernel, chosen by the host for a single discharge
+// whose workgroups each start with at least 2 kPassDynMinShare slots).  A static cut into
+// equal slot ranges (run_range) left the last workgroup ~20 us behind the mean at 5x10^7
+// particles: the cost of a range varies from step to step.  Here each workgroup's waves take
+// sub-blocks of kSubIters iterations over 64 consecutive slots from an LDS counter, so a
+// wave that runs ahead takes more; and where every workgroup's share of a species is at
+// least kPassDynMinShare slots, the slots of the species are cut into blocks of kBlockSlots
+// that the workgroups serving it take from a global counter (kRepBlock + S), so the
+// workgroups finish together.  The wave holding a block's first sub-block fetches the
+// workgroup's block two ahead, once the block one ahead has been published, so the ids of a
+// workgroup's blocks increase and its first kNoBlock means the species is done.  Every wait
+// is bounded (kErrSchedule).  Smaller discharges and the batched launch keep the static cut
+// (pass_kernel): there the per-wave sub-blocks were slower (measured: +4 % on the
+// 2x10^6-particle discharge, +13 % on the 64-discharge batch).
+constexpr int kSubIters = 4;
+constexpr int kSubSlots = 64 * kSubIters;
+constexpr int kBlockSubs = 16;
+constexpr int kBlockSlots = kSubSlots * kBlockSubs;
+static_assert(kPassDynMinShare == 8 * kBlockSlots, "a workgroup takes at least 8 blocks");
+constexpr uint32_t kNoBlock = 0xFFFFFFFFu;
+constexpr int kSpinLimit = 1 << 20;
+
+// Where a workgroup's slots of a species come from: blocks from gctr (dyn), else its static
+// range [b, e).
+struct Dist {
+    unsigned long long* gctr;
+    uint64_t nblk;
+    int64_t b, e;
+    bool dyn;
+};
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The tagged entry of the workgroup's block j, once published.
+__device__ __forceinline__ uint64_t ring_wait(const Lds& L, uint32_t j) {
+    for (int k = 0; k < kSpinLimit; ++k) {
+        const uint64_t v =
+            uniform64(__hip_atomic_load(&L.ring[j % kPassRing], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if ((uint32_t)(v >> 32) == j) return v;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if ((threadIdx.x & 63) == 0) atomicOr(&L.cnt[kCntErr], kErrSchedule);
+    return ((uint64_t)j << 32) | kNoBlock;
+}
+
+__device__ __forceinline__ void ring_publish(const Lds& L, uint32_t j, uint32_t id) {
+    if ((threadIdx.x & 63) == 0)
+        __hip_atomic_store(&L.ring[j % kPassRing], ((uint64_t)j << 32) | id, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Start of the workgroup's distribution for a species (thread 0, before a barrier); with
+// blocks, blocks 0 and 1 with one global atomic.
+__device__ __forceinline__ void ring_start(const Lds& L, const Dist& d) {
+    L.sub[0] = 0u;
+    if (!d.dyn) return;
+    const uint64_t b = atomicAdd(d.gctr, 2ull);
+    for (uint32_t k = 2; k < (uint32_t)kPassRing; ++k) L.ring[k] = ~0ull;   // tags no j reaches
+    L.ring[0] = b < d.nblk ? b : (uint64_t)kNoBlock;
+    L.ring[1] = (1ull << 32) | (b + 1 < d.nblk ? b + 1 : (uint64_t)kNoBlock);
+}
+
+// First slot of this wave's next sub-block, or -1 when the workgroup's part of the species
+// (slots below ns) is done (wave-uniform).
+__device__ __forceinline__ int64_t next_sub(const Lds& L, const Dist& d, int64_t ns) {
+    uint32_t s = 0;
+    if ((threadIdx.x & 63) == 0) s = atomicAdd(L.sub, 1u);
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (!d.dyn) {
+        const int64_t base = d.b + (int64_t)s * kSubSlots;
+        return base < d.e ? base : -1;
+    }
+    unsigned long long* gctr = d.gctr;
+    const uint64_t nblk = d.nblk;
+    const uint32_t j = s / kBlockSubs, q = s % kBlockSubs;
+    if (q == 0) {
+        uint32_t id = kNoBlock;
+        if ((uint32_t)ring_wait(L, j + 1) != kNoBlock) {
+            uint64_t b = 0;
+            if ((threadIdx.x & 63) == 0) b = atomicAdd(gctr, 1ull);
+            b = uniform64(b);
+            if (b < nblk) id = (uint32_t)b;
+        }
+        ring_publish(L, j + 2, id);
+    }
+    const uint32_t id = (uint32_t)ring_wait(L, j);
+    if (id == kNoBlock) return -1;
+    const int64_t base = (int64_t)id * kBlockSlots + (int64_t)q * kSubSlots;
+    return base < ns ? base : -1;
+}
+
+// The slots of species S, one particle per lane per iteration, in sub-blocks taken as
+// above, with the next iteration's loads issued before the current particle is processed
+// (also across sub-blocks; one copy of the particle code per species keeps the kernel
+// within the instruction cache).  While the current and the next sub-block are whole, loads
+// and stores are unconditional, so the wait for the current particle's data does not also
+// wait for the next one's loads.
+template <int MODE, int S>
+__device__ __forceinline__ void run_blocks(const Params& P, const Lds& L, const Dist& d, uint32_t stepf, unsigned cur,
+                                           int64_t ns0, int64_t ns1, bool sample) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wq = (tid >> 6) * kWaveQueue;
+    const int64_t ns = d.dyn ? (S ? ns1 : ns0) : d.e;   // slots below ns are this workgroup's to take
+    ChargeRun qrun;
+    MomentRun mrun;
+    unsigned nq = 0;   // entries in this wave's queue (wave-uniform)
+    int64_t base = next_sub(L, d, ns);
+    if (base >= 0) {
+        int k = 0;   // iteration within the sub-block
+        int64_t i = base + lane;
+        Regs r = load_particle_if<MODE, S>(P, cur, i, ns);
+        for (;;) {
+            int64_t nb = base;
+            int nk = k + 1;
+            if (nk == kSubIters) {
+                nb = next_sub(L, d, ns);
+                nk = 0;
+            }
+            if (nb < 0) break;
+            const int64_t in = nb + (int64_t)nk * 64 + lane;
+            if (base + kSubSlots <= ns && nb + kSubSlots <= ns) {
+                const Regs rn = load_particle<MODE, S>(P, cur, in);
+                process_particle<MODE, S, true>(P, L, i, ns, r, stepf, cur, ns0, ns1, sample, lane, wq, qrun, mrun,
+                                                nq);
+                r = rn;
+            } else {
+                const Regs rn = load_particle_if<MODE, S>(P, cur, in, ns);
+                process_particle<MODE, S, false>(P, L, i, ns, r, stepf, cur, ns0, ns1, sample, lane, wq, qrun,
+                                                 mrun, nq);
+                r = rn;
+            }
+            base = nb;
+            k = nk;
+            i = in;
+        }
+        // the wave's last iteration, with nothing to load after it
+        process_particle<MODE, S, false>(P, L, i, ns, r, stepf, cur, ns0, ns1, sample, lane, wq, qrun, mrun, nq);
+    }
+    if (S == 1) {
+        flush_run(L, qrun);
+        if (sample) flush_run(L, mrun);
+    }
+    if ((MODE & kComplete) && nq > 0u) drain_queue<MODE, S>(P, L, wq, nq, nq, stepf, cur, ns0, ns1, sample);
+}
+
 // ----------------------------------------------------------------------------------
 // Poisson solve (one workgroup).
 // ----------------------------------------------------------------------------------
@@ -1087,14 +1240,16 @@ __device__ void epilogue(const Params& P, unsigned char* smem, int64_t step, uns
 }
 
 // One launch's work of workgroup wg of the G workgroups that serve discharge P.
-template <int MODE>
+template <int MODE, bool DYN>
 __device__ __forceinline__ void pass_body(const Params& P, unsigned char* smem, const int wg, const int G) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int nn = P.n_cells + 1;
     Ctrl* C = P.ctrl;
     Lds L;
     L.cnt = reinterpret_cast<uint32_t*>(smem);
-    L.Q = reinterpret_cast<unsigned long long*>(smem + kCntSlots * 4);
+    L.ring = reinterpret_cast<unsigned long long*>(smem + kCntSlots * 4);
+    L.sub = reinterpret_cast<uint32_t*>(L.ring + kPassRing);
+    L.Q = reinterpret_cast<unsigned long long*>(smem + kCntSlots * 4 + kPassRingBytes);
     L.M = L.Q + nn;
     L.E = reinterpret_cast<float*>(L.M + nn);
     L.U = L.E + nn;
@@ -1119,10 +1274,12 @@ __device__ __forceinline__ void pass_body(const Params& P, unsigned char* smem, 
     if (MODE & kComplete)
         for (int i = tid; i <= kNullBins; i += nt) L.U[i] = P.nullbound[i];
 
-    // Workgroups are species-pure: the first G_e take the electrons, the rest the ions, in
+    // Workgroups are species-pure: the first G_e serve the electrons, the rest the ions, G_e in
     // proportion to the expected work, slot counts weighted by the measured cost per slot of
-    // each species (a single workgroup takes both, one after the other).
+    // each species (a single workgroup serves both, one after the other).  Within a species
+    // the slots go to waves in sub-blocks as they ask for them (run_blocks).
     int64_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+    bool dyn0 = false, dyn1 = false;   // blocks from the global counter (DYN only)
     if (G == 1) {
         e0 = ns0;
         e1 = ns1;
@@ -1137,11 +1294,13 @@ __device__ __forceinline__ void pass_body(const Params& P, unsigned char* smem, 
             const int64_t per = (ns0 + Ge - 1) / Ge;
             b0 = min((int64_t)b * per, ns0);
             e0 = min(b0 + per, ns0);
+            dyn0 = DYN && Ge > 1 && per >= kPassDynMinShare;
         } else {
             const int Gi = G - Ge;
             const int64_t per = (ns1 + Gi - 1) / Gi;
             b1 = min((int64_t)(b - Ge) * per, ns1);
             e1 = min(b1 + per, ns1);
+            dyn1 = DYN && Gi > 1 && per >= kPassDynMinShare;
         }
     }
     for (int s = 0; s < 2; ++s) {
@@ -1152,11 +1311,21 @@ __device__ __forceinline__ void pass_body(const Params& P, unsigned char* smem, 
             L.Q[i] = 0ull;
             if (sample) L.M[i] = 0ull;
         }
+        const Dist d{P.rep + kRepBlock + s, (uint64_t)(((s ? ns1 : ns0) + kBlockSlots - 1) / kBlockSlots), b, e,
+                     s ? dyn1 : dyn0};
+        if (DYN && tid == 0) ring_start(L, d);
         __syncthreads();
-        if (s == 0)
-            run_range<MODE, 0>(P, L, b, e, stepf, cur, ns0, ns1, sample);
-        else
-            run_range<MODE, 1>(P, L, b, e, stepf, cur, ns0, ns1, sample);
+        if (DYN) {
+            if (s == 0)
+                run_blocks<MODE, 0>(P, L, d, stepf, cur, ns0, ns1, sample);
+            else
+                run_blocks<MODE, 1>(P, L, d, stepf, cur, ns0, ns1, sample);
+        } else {
+            if (s == 0)
+                run_range<MODE, 0>(P, L, b, e, stepf, cur, ns0, ns1, sample);
+            else
+                run_range<MODE, 1>(P, L, b, e, stepf, cur, ns0, ns1, sample);
+        }
         __syncthreads();
         if (tid == 0 && (MODE & kAdvance)) {   // balance data for the next launch's split
             L.cnt[kCntTicks + s] = (uint32_t)(__builtin_amdgcn_s_memrealtime() - t0);
@@ -1204,7 +1373,14 @@ __device__ __forceinline__ void pass_body(const Params& P, unsigned char* smem, 
 template <int MODE>
 __global__ void __launch_bounds__(1024) pass_kernel(Params P) {
     extern __shared__ __align__(16) unsigned char smem[];
-    pass_body<MODE>(P, smem, blockIdx.x, gridDim.x);
+    pass_body<MODE, false>(P, smem, blockIdx.x, gridDim.x);
+}
+
+// The same launch with the dynamic work distribution (run_blocks).
+template <int MODE>
+__global__ void __launch_bounds__(1024) pass_dyn_kernel(Params P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    pass_body<MODE, true>(P, smem, blockIdx.x, gridDim.x);
 }
 
 // Several independent discharges advanced by one launch: discharge d owns workgroups
@@ -1220,7 +1396,7 @@ __global__ void __launch_bounds__(1024) pass_batch_kernel(const Params* __restri
         const int mid = (lo + hi) >> 1;
         if (seg[mid] <= b) lo = mid; else hi = mid;
     }
-    pass_body<MODE>(batch[lo], smem, b - seg[lo], seg[lo + 1] - seg[lo]);
+    pass_body<MODE, false>(batch[lo], smem, b - seg[lo], seg[lo + 1] - seg[lo]);
 }
 
 // ----------------------------------------------------------------------------------
@@ -1768,28 +1944,35 @@ __global__ void reset_window_kernel(Params P) {
 // ----------------------------------------------------------------------------------
 // Launchers (called by the host library).
 // ----------------------------------------------------------------------------------
-hipError_t launch_pass(int mode, const Params& P, int blocks, int threads, size_t lds, hipStream_t st) {
-    switch (mode) {
-        case kComplete | kAdvance | kRecord:
-            hipLaunchKernelGGL(pass_kernel<kComplete | kAdvance | kRecord>, dim3(blocks), dim3(threads), lds, st, P);
-            break;
-        case kComplete | kRecord:
-            hipLaunchKernelGGL(pass_kernel<kComplete | kRecord>, dim3(blocks), dim3(threads), lds, st, P);
-            break;
-        case kComplete | kAdvance:
-            hipLaunchKernelGGL(pass_kernel<kComplete | kAdvance>, dim3(blocks), dim3(threads), lds, st, P);
-            break;
-        case kAdvance:
-            hipLaunchKernelGGL(pass_kernel<kAdvance>, dim3(blocks), dim3(threads), lds, st, P);
-            break;
-        case kComplete:
-            hipLaunchKernelGGL(pass_kernel<kComplete>, dim3(blocks), dim3(threads), lds, st, P);
-            break;
-        case kDeposit:
-            hipLaunchKernelGGL(pass_kernel<kDeposit>, dim3(blocks), dim3(threads), lds, st, P);
-            break;
-        default:
-            return hipErrorInvalidValue;
+#define PIC_PASS_SWITCH(KERNEL)                                                                                    \
+    switch (mode) {                                                                                                \
+        case kComplete | kAdvance | kRecord:                                                                       \
+            hipLaunchKernelGGL(KERNEL<kComplete | kAdvance | kRecord>, dim3(blocks), dim3(threads), lds, st, P); \
+            break;                                                                                                 \
+        case kComplete | kRecord:                                                                                  \
+            hipLaunchKernelGGL(KERNEL<kComplete | kRecord>, dim3(blocks), dim3(threads), lds, st, P);            \
+            break;                                                                                                 \
+        case kComplete | kAdvance:                                                                                 \
+            hipLaunchKernelGGL(KERNEL<kComplete | kAdvance>, dim3(blocks), dim3(threads), lds, st, P);           \
+            break;                                                                                                 \
+        case kAdvance:                                                                                             \
+            hipLaunchKernelGGL(KERNEL<kAdvance>, dim3(blocks), dim3(threads), lds, st, P);                       \
+            break;                                                                                                 \
+        case kComplete:                                                                                            \
+            hipLaunchKernelGGL(KERNEL<kComplete>, dim3(blocks), dim3(threads), lds, st, P);                      \
+            break;                                                                                                 \
+        case kDeposit:                                                                                             \
+            hipLaunchKernelGGL(KERNEL<kDeposit>, dim3(blocks), dim3(threads), lds, st, P);                       \
+            break;                                                                                                 \
+        default:                                                                                                   \
+            return hipErrorInvalidValue;                                                                           \
+    }
+
+hipError_t launch_pass(int mode, const Params& P, int blocks, int threads, size_t lds, hipStream_t st, bool dyn) {
+    if (dyn) {
+        PIC_PASS_SWITCH(pass_dyn_kernel)
+    } else {
+        PIC_PASS_SWITCH(pass_kernel)
     }
     return hipGetLastError();
 }
@@ -1959,23 +2142,22 @@ hipError_t set_pass_lds_limit(size_t bytes) {
     std::lock_guard<std::mutex> lock(mu);
     if (bytes <= limit) return hipSuccess;
     const int b = (int)bytes;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete | kAdvance>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kAdvance>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kDeposit>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete | kAdvance | kRecord>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_kernel<kComplete | kRecord>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    const void* kernels[] = {
+        reinterpret_cast<const void*>(&pass_kernel<kComplete | kAdvance>),
+        reinterpret_cast<const void*>(&pass_kernel<kAdvance>),
+        reinterpret_cast<const void*>(&pass_kernel<kComplete>),
+        reinterpret_cast<const void*>(&pass_kernel<kDeposit>),
+        reinterpret_cast<const void*>(&pass_kernel<kComplete | kAdvance | kRecord>),
+        reinterpret_cast<const void*>(&pass_kernel<kComplete | kRecord>),
+        reinterpret_cast<const void*>(&pass_dyn_kernel<kComplete | kAdvance>),
+        reinterpret_cast<const void*>(&pass_dyn_kernel<kAdvance>),
+        reinterpret_cast<const void*>(&pass_dyn_kernel<kComplete>),
+        reinterpret_cast<const void*>(&pass_dyn_kernel<kDeposit>),
+        reinterpret_cast<const void*>(&pass_dyn_kernel<kComplete | kAdvance | kRecord>),
+        reinterpret_cast<const void*>(&pass_dyn_kernel<kComplete | kRecord>)};
+    hipError_t e = hipSuccess;
+    for (const void* k : kernels)
+        if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e == hipSuccess) limit = bytes;
     return e;
 }

@@ -20,8 +20,18 @@ constexpr int kMaxSortBlocks = 4096;  // workgroups of the periodic reordering
 // serialise on the control block's few cache lines; the last workgroup sums the sets.
 constexpr int kRepSets = 16;
 constexpr int kRepStride = 32;        // 64-bit words per set
+// Set 0 also holds the two species' block counters of the particle pass (kRepBlock + s); the
+// last workgroup clears every set, so each launch starts them at zero.
 enum : int { kRepAbs = 0, kRepColl = 4, kRepViol = 20, kRepErr = 22, kRepTicks = 23, kRepParts = 25,
-             kRepDone = 27 };
+             kRepDone = 27, kRepBlock = 28 };
+// LDS of the particle pass's work distribution: a ring of kPassRing tagged block ids and the
+// workgroup's sub-block counter (padded to 8 bytes).
+constexpr int kPassRing = 8;
+constexpr int kPassRingBytes = kPassRing * 8 + 8;
+// The dynamic distribution's blocks go to a species' workgroups only where each holds at least
+// this many of its slots (8 blocks of 4096); the host picks the dynamic pass for a single
+// discharge whose workgroups start with twice that.
+constexpr int64_t kPassDynMinShare = 8 * 4096;
 // Charge deposit in fixed point: a particle's two cloud-in-cell weights are integers
 // summing to 2^24, accumulated with integer atomics, so the node charges are exact and
 // independent of the order of accumulation (bitwise reproducible runs).
@@ -50,6 +60,7 @@ constexpr uint32_t kErrCapacity = 1u;   // particle storage exhausted by births
 constexpr uint32_t kErrNumeric = 2u;    // non-finite coordinate
 constexpr uint32_t kErrBirths = 4u;     // per-step birth buffer exhausted
 constexpr uint32_t kErrIds = 8u;        // 32-bit id space exhausted
+constexpr uint32_t kErrSchedule = 16u;  // a wait of the work distribution reached its bound (internal)
 
 // Control block: one per discharge, device resident, read by every kernel at launch and
 // updated by the last workgroup of each launch (so it stays valid under graph replay).

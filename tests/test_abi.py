@@ -151,6 +151,7 @@ def test_new_entry_points_reject_null_on_host():
     n = C.c_int64()
     assert L.pic_batch_graph_launches(None, C.byref(n)) == B.PIC_EINVAL
     assert L.pic_graph_launches(None, C.byref(n)) == B.PIC_EINVAL
+    assert L.pic_launch_shape(None, None, None, None) == B.PIC_EINVAL
     assert L.mlp_num_params(None, C.byref(n)) == B.PIC_EINVAL
 
 
