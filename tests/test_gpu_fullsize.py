@@ -28,6 +28,8 @@ def test_full_size_single_step(name):
     disc = CASES[name]()
     log(f"full-size parity: {name} N={disc.n_super} cells={disc.n_cells}")
     with B.Discharge(disc) as d:
+        # the launch the benchmark times: the dynamic work distribution at 4096 cells
+        assert d.launch_shape()[2] == (name == "large_argon")
         d.step(100)
         c0 = d.counters()
         o = Oracle(disc, load=False)

@@ -96,6 +96,26 @@ def test_seeded_run_is_reproducible():
     assert runs[0][2]["next_id"] == runs[1][2]["next_id"]
 
 
+def test_dynamic_work_distribution_equals_static_cut():
+    """The pass that takes blocks of slots from a per-species counter (chosen when every
+    workgroup starts with at least 65536 slots) moves every particle as the fixed slot ranges
+    do: same state per id, same collision counts and ids, same fields, over reorderings."""
+    disc = W.small_argon(seed=9, n_super=300_000)
+    runs = []
+    for blocks, dynamic in ((4, True), (64, False)):
+        with B.Discharge(disc, launch_blocks=blocks) as d:
+            assert d.launch_shape() == (blocks, 256, dynamic)
+            d.step(150)
+            runs.append((d.particles(0), d.particles(1), d.counters(), d.fields()))
+    for s in (0, 1):
+        _same_state(runs[0][s], runs[1][s])
+    assert runs[0][2]["collisions"].tolist() == runs[1][2]["collisions"].tolist()
+    assert runs[0][2]["next_id"] == runs[1][2]["next_id"]
+    assert runs[0][2]["n_alive"] == runs[1][2]["n_alive"]
+    for key in ("E", "phi"):
+        assert np.array_equal(runs[0][3][key], runs[1][3][key]), key
+
+
 def test_checkpoint_resume_equals_continuous_run():
     disc = W.small_argon(seed=6)
     with B.Discharge(disc) as d:
