@@ -156,13 +156,23 @@ def test_single_step_parity(case):
             mg = B.pic_moments(d.h, nn)
             mo = o.moments()
             assert mg["n_samples"] == mo["n_samples"] == 1
-            for key in ("n_e", "n_i", "flux_i", "phi"):
+            # One step from the same state: FP32 positions in cell units (at most 128 cells here)
+            # round a cloud-in-cell weight by <= 3.8e-6, so densities and phi agree within 4e-6
+            # of their maxima; velocities agree within 1e-5 of v_th, which the bulk-to-sheath
+            # ratio of the ion flux carries to ~1e-5 of its maximum.
+            errs = {}
+            for key, tol in (("n_e", 1e-5), ("n_i", 1e-5), ("flux_i", 1e-4), ("phi", 1e-5)):
                 scale = np.abs(mo[key]).max() + 1e-30
-                assert np.max(np.abs(mg[key] - mo[key])) <= 2e-4 * scale, key
+                errs[key] = np.max(np.abs(mg[key] - mo[key])) / scale
+                assert errs[key] <= tol, key
             both = np.isfinite(mo["mean_energy_e"]) & np.isfinite(mg["mean_energy_e"])
             assert np.array_equal(np.isfinite(mo["mean_energy_e"]), np.isfinite(mg["mean_energy_e"]))
+            # a node's mean energy is a ratio of weighted sums: where few electrons reach a node
+            # with small weights, a 4e-6 weight change moves it by far more than the sums' error
             rel = np.abs(mg["mean_energy_e"][both] - mo["mean_energy_e"][both]) / np.maximum(mo["mean_energy_e"][both], 1e-3)
             assert rel.max(initial=0) <= 2e-3
+            log("  one-sample moments, largest error / max: " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items())
+                + f"; mean energy relative {rel.max(initial=0):.1e}; unsure {len(unsure[0])}+{len(unsure[1])}")
         c = d.counters()
         assert c["numax_violations"] == (0, 0)
         log(f"  births over checkpoints: {total_births}, most in one step: {max_births}")
